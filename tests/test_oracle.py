@@ -1,0 +1,179 @@
+"""CPU oracle pinned to the paper and to mathematics (no GPU needed)."""
+
+import numpy as np
+import pytest
+
+from oracle import adjoint, conv
+import oracle_pins as P
+import workloads
+
+
+def test_fft_golden():
+    P.pin_fft_golden(conv.fft)
+
+
+def test_dft_definition_golden():
+    P.pin_fft_golden(conv.dft)
+
+
+def test_fft_vs_bruteforce():
+    P.pin_fft_vs_bruteforce(conv.fft)
+
+
+def test_fft_closed_forms_and_parseval():
+    P.pin_fft_closed_forms(conv.fft)
+
+
+def test_fft_vs_library():
+    P.pin_fft_library(conv.fft)
+
+
+def test_ifft_roundtrip():
+    P.pin_ifft_roundtrip(conv.fft, conv.ifft)
+
+
+def test_fft_rejects_bad_length():
+    with pytest.raises(ValueError):
+        conv.fft(np.ones(6))
+
+
+@pytest.mark.parametrize("impl", ["direct_conv", "direct_conv_loops", "full_fft_conv"])
+def test_conv_golden(impl):
+    P.pin_conv_golden(getattr(conv, impl))
+
+
+def test_ols_golden_small_segments():
+    P.pin_conv_golden(lambda s, h: conv.ols_conv(s, h, 2))
+    P.pin_ols_golden(conv.ols_conv)
+
+
+@pytest.mark.parametrize("impl", ["direct_conv", "full_fft_conv"])
+def test_conv_bruteforce(impl):
+    P.pin_conv_bruteforce(getattr(conv, impl))
+
+
+def test_direct_conv_loops_is_bruteforce():
+    P.pin_conv_bruteforce(conv.direct_conv_loops)
+
+
+@pytest.mark.parametrize("impl", ["direct_conv", "full_fft_conv"])
+def test_conv_library(impl):
+    P.pin_conv_library(getattr(conv, impl))
+
+
+@pytest.mark.parametrize("impl", ["direct_conv", "full_fft_conv"])
+def test_conv_closed_forms(impl):
+    P.pin_conv_closed_forms(getattr(conv, impl))
+
+
+def test_conv_linearity():
+    P.pin_conv_linearity(conv.direct_conv)
+
+
+def test_direct_conv_chunking():
+    rng = np.random.default_rng(3)
+    s = P.rand_c(rng, 1000)
+    h = P.rand_c(rng, 2, 33)
+    P._close(conv.direct_conv(s, h, chunk=7), conv.direct_conv(s, h), 1e-13, "chunked")
+
+
+def test_direct_conv_at():
+    rng = np.random.default_rng(4)
+    s = P.rand_c(rng, 2000)
+    h = P.rand_c(rng, 3, 50)
+    idx = np.array([0, 1, 48, 49, 50, 777, 1999])
+    P._close(conv.direct_conv_at(s, h, idx), conv.direct_conv(s, h)[:, idx], 1e-13, "direct_conv_at")
+    with pytest.raises(IndexError):
+        conv.direct_conv_at(s, h, [2000])
+
+
+def test_circular_alias_golden():
+    P.pin_circular_alias(conv.fft, conv.ifft)
+
+
+def test_ols_discard_count_bruteforce():
+    """A causal filter of length M corrupts exactly circular positions 0..M-2
+    (sec. 3.2: M-1 discarded samples; footnote to eq. 2: causal filters alias
+    the start).  Brute force on a tiny segment."""
+    rng = np.random.default_rng(8)
+    N = 16
+    for M in (1, 2, 5, 16):
+        x = P.rand_c(rng, N)
+        h = P.rand_c(rng, M)
+        circ = np.zeros(N, dtype=np.complex128)
+        lin = np.zeros(N, dtype=np.complex128)
+        for n in range(N):
+            for k in range(M):
+                circ[n] += x[(n - k) % N] * h[k]
+                if n - k >= 0:
+                    lin[n] += x[n - k] * h[k]
+        P._close(conv.ifft(conv.fft(x) * conv.fft(np.concatenate([h, np.zeros(N - M)]))), circ, 1e-12, "fft circ")
+        bad = np.abs(circ - lin) > 1e-9
+        assert list(np.nonzero(bad)[0]) == list(range(M - 1)), (M, np.nonzero(bad)[0])
+
+
+def test_ols_matches_definition():
+    P.pin_ols_matches_definition(conv.ols_conv, None)
+
+
+def test_ols_segment_invariance():
+    P.pin_ols_segment_invariance(conv.ols_conv)
+
+
+def test_ols_filters_independent():
+    P.pin_ols_filters_independent(conv.ols_conv)
+
+
+def test_ols_rejects_bad_geometry():
+    s = np.ones(10)
+    with pytest.raises(ValueError):
+        conv.ols_conv(s, np.ones((1, 9)), 8)
+    with pytest.raises(ValueError):
+        conv.ols_conv(s, np.ones((1, 4)), 12)
+    with pytest.raises(ValueError):
+        conv.ols_conv(s, np.ones((1, 4)), 8, 6)
+
+
+def test_direct_vs_ols_medium_fp64():
+    """Two independent FP64 routes agree to ~1e-13 on a workload-shaped input."""
+    s, h = workloads.make_signal_filters(1 << 15, 4, 256, seed=123)
+    a = conv.direct_conv(s, h)
+    b = conv.ols_conv(s, h, 2048)
+    rel = np.linalg.norm(a - b, axis=1) / np.linalg.norm(a, axis=1)
+    assert np.all(rel < 1e-13), rel
+
+
+def test_adjoint_loops_vs_vectorised():
+    rng = np.random.default_rng(9)
+    s = P.rand_c(rng, 40)
+    h = P.rand_c(rng, 2, 7)
+    g = P.rand_c(rng, 2, 40)
+    P._close(adjoint.grad_signal(g, h), adjoint.grad_signal_loops(g, h), 1e-12, "ds")
+    P._close(adjoint.grad_filters(g, s, 7), adjoint.grad_filters_loops(g, s, 7), 1e-12, "dh")
+    P._close(adjoint.grad_signal(g, h, chunk=3), adjoint.grad_signal(g, h), 1e-13, "ds chunk")
+    P._close(adjoint.grad_filters(g, s, 7, chunk=3), adjoint.grad_filters(g, s, 7), 1e-13, "dh chunk")
+
+
+@pytest.mark.parametrize("pair", ["vectorised", "loops"])
+def test_adjoint_dot_product(pair):
+    if pair == "vectorised":
+        P.pin_adjoint_dot_product(conv.direct_conv, adjoint.grad_signal, adjoint.grad_filters)
+    else:
+        P.pin_adjoint_dot_product(conv.direct_conv_loops, adjoint.grad_signal_loops, adjoint.grad_filters_loops)
+
+
+def test_adjoint_finite_differences():
+    P.pin_adjoint_finite_differences(conv.direct_conv, adjoint.grad_signal, adjoint.grad_filters)
+
+
+def test_workload_generator_recipe():
+    s, h = workloads.make_signal_filters(1000, 3, 64, seed=7)
+    assert s.dtype == np.complex64 and h.dtype == np.complex64
+    assert s.shape == (1000,) and h.shape == (3, 64)
+    assert np.all(np.abs(s.real) <= 1) and np.all(np.abs(s.imag) <= 1)
+    s2, h2 = workloads.make_signal_filters(1000, 3, 64, seed=7)
+    assert np.array_equal(s, s2) and np.array_equal(h, h2)
+    # filter variance per component ~ 1/M
+    big = workloads.make_signal_filters(10, 64, 1024, seed=8)[1]
+    v = np.var(big.real) * 1024
+    assert 0.9 < v < 1.1

@@ -1,0 +1,170 @@
+"""The pins must catch plausible mistakes planted in (copies of) the oracle.
+
+Every mutant below is a copy of an oracle routine with one planted mistake (a
+wrong sign, a dropped term, an off-by-one index, a transposed operand).  Each
+must fail at least one pin.  CPU only; nothing here touches the GPU path.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import adjoint, conv
+import oracle_pins as P
+
+
+def _fft_mutant(sign_flip=False, skip_bitrev=False, twiddle_half=False):
+    def core(x, sign):
+        x = np.asarray(x, dtype=np.complex128)
+        N = x.shape[-1]
+        if N & (N - 1):
+            raise ValueError
+        if sign_flip:
+            sign = -sign
+        y = x.copy() if skip_bitrev else x[..., conv._bit_reverse_indices(N)].copy()
+        m = 2
+        while m <= N:
+            half = m // 2
+            k = np.arange(half)
+            w = np.exp(sign * 2j * np.pi * k / (2 * m if twiddle_half else m))
+            b = y.reshape(y.shape[:-1] + (N // m, m))
+            u = b[..., :half].copy()
+            t = b[..., half:] * w
+            b[..., :half] = u + t
+            b[..., half:] = u - t
+            y = b.reshape(y.shape)
+            m *= 2
+        return y
+    return (lambda x: core(x, -1.0)), (lambda X: core(X, 1.0) / np.shape(X)[-1])
+
+
+def _ols_mutant(discard_shift=0, compound=False, no_history=False, hop_fix=0):
+    def ols(s, h, N, hop=None):
+        s = np.asarray(s, dtype=np.complex128)
+        h = np.atleast_2d(np.asarray(h, dtype=np.complex128))
+        K, M = h.shape
+        Ns = s.shape[0]
+        L = N - M + 1
+        H = (L if hop is None else hop) + hop_fix
+        H = max(H, 1)
+        y = np.zeros((K, Ns), dtype=np.complex128)
+        if Ns == 0:
+            return y
+        nseg = -(-Ns // H)
+        F = np.fft.fft(np.concatenate([h, np.zeros((K, N - M))], axis=1))
+        hist = 0 if no_history else M - 1
+        xp = np.zeros((nseg - 1) * H + N + M, dtype=np.complex128)
+        xp[hist:hist + Ns] = s
+        segs = xp[np.arange(nseg)[:, None] * H + np.arange(N)[None, :]]
+        A = np.fft.fft(segs)
+        d = M - 1 + discard_shift
+        for r in range(K):
+            if compound:
+                A = A * F[r]
+                a = np.fft.ifft(A)
+            else:
+                a = np.fft.ifft(A * F[r])
+            out = a[:, d:d + H]
+            if out.shape[1] < H:
+                out = np.concatenate([out, np.zeros((nseg, H - out.shape[1]))], axis=1)
+            y[r] = out.reshape(-1)[:Ns]
+        return y
+    return ols
+
+
+def _expect_caught(*checks):
+    caught = 0
+    for fn in checks:
+        try:
+            fn()
+        except (AssertionError, ValueError, IndexError):
+            caught += 1
+    assert caught > 0, "planted mistake was not caught by any pin"
+
+
+@pytest.mark.parametrize("kw", [dict(sign_flip=True), dict(skip_bitrev=True), dict(twiddle_half=True)])
+def test_fft_mutants_caught(kw):
+    f, fi = _fft_mutant(**kw)
+    _expect_caught(lambda: P.pin_fft_golden(f), lambda: P.pin_fft_vs_bruteforce(f),
+                   lambda: P.pin_fft_closed_forms(f))
+
+
+def test_fft_mutant_control():
+    f, fi = _fft_mutant()
+    P.pin_fft_golden(f)
+    P.pin_fft_vs_bruteforce(f)
+    P.pin_ifft_roundtrip(f, fi)
+
+
+def _conv_correlation(s, h):
+    s = np.asarray(s, dtype=np.complex128)
+    h = np.atleast_2d(h)
+    K, M = h.shape
+    Ns = len(s)
+    y = np.zeros((K, Ns), dtype=np.complex128)
+    for r in range(K):
+        for n in range(Ns):
+            for k in range(M):
+                if n + k < Ns:
+                    y[r, n] += s[n + k] * h[r, k]
+    return y
+
+
+def _conv_dropped_tap(s, h):
+    h = np.atleast_2d(np.asarray(h, dtype=np.complex128)).copy()
+    h[:, -1] = 0
+    return conv.direct_conv(s, h)
+
+
+def _conv_transposed_filter(s, h):
+    return conv.direct_conv(s, np.atleast_2d(h)[:, ::-1])
+
+
+def _conv_conjugated(s, h):
+    return conv.direct_conv(s, np.conj(np.atleast_2d(h)))
+
+
+@pytest.mark.parametrize("mut", [_conv_correlation, _conv_dropped_tap, _conv_transposed_filter, _conv_conjugated])
+def test_conv_mutants_caught(mut):
+    _expect_caught(lambda: P.pin_conv_golden(mut), lambda: P.pin_conv_bruteforce(mut),
+                   lambda: P.pin_conv_closed_forms(mut))
+
+
+@pytest.mark.parametrize("kw", [dict(discard_shift=-1), dict(discard_shift=1), dict(compound=True),
+                                dict(no_history=True), dict(hop_fix=1)])
+def test_ols_mutants_caught(kw):
+    ols = _ols_mutant(**kw)
+    _expect_caught(lambda: P.pin_ols_golden(ols), lambda: P.pin_ols_matches_definition(ols, None),
+                   lambda: P.pin_ols_filters_independent(ols), lambda: P.pin_ols_segment_invariance(ols))
+
+
+def test_ols_mutant_control():
+    ols = _ols_mutant()
+    P.pin_ols_golden(ols)
+    P.pin_ols_matches_definition(ols, None)
+    P.pin_ols_filters_independent(ols)
+
+
+def _ds_no_conj(g, h):
+    return adjoint.grad_signal(g, np.conj(h))
+
+
+def _ds_wrong_dir(g, h):
+    g = np.asarray(g)
+    K, Ns = g.shape
+    out = np.zeros(Ns, dtype=np.complex128)
+    y = conv.direct_conv(np.zeros(Ns), h)  # placeholder shape
+    for r in range(K):
+        out += conv.direct_conv(g[r], np.conj(h[r:r + 1]))[0]  # convolution instead of correlation
+    return out + 0 * y[0]
+
+
+def _dh_shift(g, s, M):
+    s = np.asarray(s)
+    return adjoint.grad_filters(g, np.concatenate([s[1:], [0]]), M)
+
+
+@pytest.mark.parametrize("ds,dh", [(_ds_no_conj, adjoint.grad_filters), (_ds_wrong_dir, adjoint.grad_filters),
+                                   (adjoint.grad_signal, _dh_shift)])
+def test_adjoint_mutants_caught(ds, dh):
+    _expect_caught(lambda: P.pin_adjoint_dot_product(conv.direct_conv, ds, dh),
+                   lambda: P.pin_adjoint_finite_differences(conv.direct_conv, ds, dh))
