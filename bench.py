@@ -1,0 +1,169 @@
+"""Benchmark: forward overlap-and-save of one long complex64 signal with a bank
+of filters on one MI355X, through the C ABI.
+
+Workload: 2^23-sample complex64 signal (re/im uniform[-1,1]), 32 complex64
+filters of 256 taps (re/im N(0,1)/sqrt(256)), FFT length 2048, output
+32 x 2^23 complex64.  Inputs are resident in HBM before timing starts.
+
+One step = one ols_forward call (the whole fused path: segment load, forward
+FFT, 32 spectrum products and inverse FFTs, discard and store).  Prints one
+JSON line.  The roofline object prices the forward kernel against the HBM
+peak using its algorithmic bytes per launch and its average launch duration
+(HIP events on the launch stream); the cpu_baseline object times the CPU
+oracle (eq. 1, float64) on a bounded prefix of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "valid output samples/sec (all filters) and % HBM roofline; fwd+bwd vs plain OLS"
+WORKLOAD = "filter_bank_2p23_k32_m256"
+KERNEL_SOURCES = ("ols_kernels.hip", "ols_fft.hpp", "ols_ops.hpp", "ols_twiddle.hpp")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1910_01972_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, bytes_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_ols_forward_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(s, h, n_sample: int):
+    """The oracle (eq. 1 by definition, float64) on the first n_sample outputs
+    of every filter row; returns samples/s and the BLAS thread count."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import conv
+
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    t0 = time.perf_counter()
+    conv.direct_conv(s[:n_sample], h)
+    dt = time.perf_counter() - t0
+    K = h.shape[0]
+    return {
+        "value": K * n_sample / dt,
+        "unit": "samples/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"eq. (1) float64 direct convolution (oracle.conv.direct_conv), first {n_sample} outputs "
+                  f"of all {K} filter rows of the same workload; {dt:.1f} s wall",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is single-GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1910_01972_amd.ols import OLSPlan
+
+    wl = workloads.WORKLOADS[WORKLOAD]
+    s_np, h_np = workloads.make_signal_filters(wl.Ns, wl.K, wl.M, seed=wl.seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = torch.from_numpy(s_np).to(dev)
+    h = torch.from_numpy(h_np).to(dev)
+    y = torch.empty((wl.K, wl.Ns), dtype=torch.complex64, device=dev)
+    plan = OLSPlan(h, N=wl.N)
+    info = plan.info()
+    launch = plan.launch()
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.forward(s, y)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        plan.forward(s, y)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(starts, ends)]))
+
+    ms_per_step = wall * 1e3 / args.steps
+    outputs = wl.K * wl.Ns
+    value = outputs / (ms_per_step * 1e-3)
+    # algorithmic HBM bytes per launch: every output written once (8 B), the
+    # signal read once (8 B/sample), the filter taps once
+    alg_bytes = 8.0 * wl.K * wl.Ns + 8.0 * wl.Ns + 8.0 * wl.K * wl.M
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(WORKLOAD, alg_bytes)
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOAD,
+            "Ns": wl.Ns, "K": wl.K, "M": wl.M, "N": info["N"], "hop": info["H"], "delay": info["D"],
+            "grid": launch["grid"], "block": launch["block"], "cus": launch["cus"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "ols_forward_kernel<2048>",
+            "kernel_ms": kernel_ms,
+            "alg_bytes_per_launch": alg_bytes,
+        },
+    }
+    plan.close()
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(s_np, h_np, args.cpu_sample)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

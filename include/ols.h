@@ -1,0 +1,152 @@
+/*
+ * ols.h -- C ABI of the MI355X (gfx950) overlap-and-save convolution library.
+ *
+ * The method: Adamek, Dimoudi, Giles, Armour, "GPU Fast Convolution via the
+ * Overlap-and-Save Method in Shared Memory".  A long complex signal s of
+ * length N_s is convolved with K short filters h_r of length M (eq. 1, sec. 1)
+ * by overlap-and-save (sec. 3.2): overlapping segments of FFT length N are
+ * transformed once, multiplied point-wise by every filter spectrum, inverse
+ * transformed, and only the unaliased samples are kept.  One fused HIP kernel
+ * does all of that per segment tile, on chip (sec. 3.4, Alg. 2).
+ *
+ * Conventions used by every entry point:
+ *   - complex64 = interleaved {float re, float im}, 8-byte aligned;
+ *   - every data pointer is a DEVICE pointer owned by the caller (the library
+ *     never frees or keeps it beyond the call);
+ *   - `stream` is a hipStream_t (NULL = the null stream); all device work is
+ *     enqueued asynchronously on it; errors inside kernels surface at the
+ *     caller's next synchronisation;
+ *   - every call validates its arguments on the host before enqueuing
+ *     anything, returns an ols_status_t and never throws or aborts; a failing
+ *     call enqueues nothing; ols_last_error() gives a message for the calling
+ *     thread's most recent failure;
+ *   - index arithmetic is 64-bit (K * N_s may exceed 2^31).
+ */
+#ifndef OLS_H_
+#define OLS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ols_plan_s* ols_plan_t;
+typedef void* ols_stream_t; /* a hipStream_t */
+
+typedef enum {
+  OLS_SUCCESS = 0,
+  OLS_ERROR_INVALID_VALUE = 1, /* null pointer, bad size, overlap, misalignment */
+  OLS_ERROR_UNSUPPORTED = 2,   /* FFT length outside {256, ..., 8192} or not a power of two */
+  OLS_ERROR_OUT_OF_MEMORY = 3, /* device allocation failed (plan creation only) */
+  OLS_ERROR_HIP = 4,           /* a HIP runtime call or kernel launch failed */
+  OLS_ERROR_INTERNAL = 5       /* unexpected exception caught at the boundary */
+} ols_status_t;
+
+/* Smallest and largest supported FFT (segment) length N. */
+#define OLS_MIN_FFT_LENGTH 256
+#define OLS_MAX_FFT_LENGTH 8192
+
+/*
+ * ols_plan -- prepare the convolution of any signal with a bank of K filters.
+ *
+ * Paper: the filters are Fourier transformed once, before the segments are
+ * processed (Fig. 1; Alg. 2, "Forward FFT of the filters"); the FFT length N
+ * is a power of two and leaves L = N - M + 1 unaliased samples per segment
+ * (sec. 3.2).
+ *
+ *   plan   out: receives the new plan (set to NULL on failure)
+ *   h      device, complex64 [K][M] row-major: the filter taps h_r[k]
+ *   K      number of filters, >= 1
+ *   M      filter length, 1 <= M <= N
+ *   N      FFT length: power of two in [256, 8192], or 0 to let the library
+ *          choose (cost model: FFT work per valid output sample)
+ *   stream the filter spectra are computed on this stream; the plan may be
+ *          used on any stream once this work is complete (the call itself
+ *          synchronises `stream` before returning, so it is)
+ *
+ * The plan owns device memory for the K filter spectra (8*K*N bytes) and the
+ * twiddle tables, all allocated here; forward calls allocate nothing.  `h`
+ * may be freed as soon as the call returns.
+ * Errors: INVALID_VALUE (null plan/h, K < 1, M < 1, M > N), UNSUPPORTED (N),
+ * OUT_OF_MEMORY, HIP.
+ */
+ols_status_t ols_plan(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int32_t N, ols_stream_t stream);
+
+/*
+ * ols_plan_update_filters -- replace the K filters of a plan (same K and M),
+ * recomputing their spectra on `stream` (stream ordered; forward calls queued
+ * later on the same stream see the new filters).  Paper: Alg. 2, forward FFT
+ * of the filters.  Errors: INVALID_VALUE (null), HIP.
+ */
+ols_status_t ols_plan_update_filters(ols_plan_t plan, const void* h, ols_stream_t stream);
+
+/*
+ * ols_plan_set_hop -- choose the segment stride H (valid outputs kept per
+ * segment).  The paper keeps L = N - M + 1 samples per segment and states
+ * that the result does not depend on the segment size (sec. 3.2), so any
+ * 1 <= H <= N - M + 1 gives the same output.  By default the library uses the
+ * largest H whose segments start on 16-sample (128-byte) boundaries:
+ * D = M - 1 rounded up to a multiple of 16 (when that still leaves room),
+ * H = N - D.  H = 0 restores the default.  Errors: INVALID_VALUE.
+ */
+ols_status_t ols_plan_set_hop(ols_plan_t plan, int32_t H);
+
+/* Plan properties: FFT length N, hop H, delay D (first kept circular sample,
+ * D >= M - 1), K and M.  Any output pointer may be NULL. */
+ols_status_t ols_plan_get_info(ols_plan_t plan, int32_t* N, int32_t* H, int32_t* D, int32_t* K, int32_t* M);
+
+/*
+ * ols_plan_get_spectra -- copy the plan's filter spectra, in natural frequency
+ * order, to `out` (device, complex64 [K][N]): out[r][m] = (1/N) *
+ * sum_{n<M} h_r[n] exp(-2 pi i m n / N) (the forward FFT of the zero-padded
+ * filter, eq. 2, with the inverse transform's 1/N folded in).  Internally the
+ * spectra are kept in the transform's digit-reversed order (sec. 3.4); this
+ * call undoes the permutation.  Enqueued on `stream`.  Errors: INVALID_VALUE, HIP.
+ */
+ols_status_t ols_plan_get_spectra(ols_plan_t plan, void* out, ols_stream_t stream);
+
+/*
+ * ols_forward -- y_r = s * h_r for every filter r (eq. 1, zero history:
+ * y_r[n] = sum_{k=0}^{M-1} h_r[k] s[n-k], s[m] = 0 for m < 0, n in [0, N_s)),
+ * computed by overlap-and-save (sec. 3.2) in one fused kernel (sec. 3.4,
+ * Alg. 2).
+ *
+ *   s    device, complex64 [N_s]
+ *   N_s  signal length, >= 0 (0 is a successful no-op)
+ *   y    device, complex64 [K][N_s] row-major, written completely; must not
+ *        overlap s (out of place only)
+ * Errors: INVALID_VALUE (null plan/s/y, N_s < 0, misaligned, overlap,
+ * K*N_s*8 overflow), HIP (launch failure).  Allocates nothing.
+ */
+ols_status_t ols_forward(ols_plan_t plan, const void* s, int64_t N_s, void* y, ols_stream_t stream);
+
+/* Release a plan and its device memory (NULL is a no-op).  The caller must
+ * make sure no enqueued work still uses the plan. */
+ols_status_t ols_plan_destroy(ols_plan_t plan);
+
+/* Static text for a status code. */
+const char* ols_status_string(ols_status_t status);
+
+/* Message of the calling thread's most recent failed call ("" if none). */
+const char* ols_last_error(void);
+
+/*
+ * ols_calibration_copy -- plain device copy of `bytes` bytes (multiple of 16,
+ * both pointers 16-byte aligned) with the library's own kernel.  Not part of
+ * the method: it is the reference workload for reading HBM traffic counters
+ * (FETCH_SIZE / WRITE_SIZE) of a kernel whose byte count is known exactly.
+ * Errors: INVALID_VALUE, HIP.
+ */
+ols_status_t ols_calibration_copy(void* dst, const void* src, size_t bytes, ols_stream_t stream);
+
+/* Number of compute units of the current device as seen by the library, and
+ * the persistent grid (workgroups) ols_forward launches for this plan. */
+ols_status_t ols_plan_get_launch(ols_plan_t plan, int32_t* grid, int32_t* block, int32_t* cus);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OLS_H_ */

@@ -1,0 +1,328 @@
+// Host emulation of the fused overlap-and-save kernels.
+//
+// Runs the very same per-lane code as the device kernels (ols_fft.hpp,
+// ols_ops.hpp) on the CPU, lane by lane, with every workgroup barrier replaced
+// by "all lanes finish this phase before any lane starts the next".  Used by
+// CPU tests to check, before anything runs on a GPU:
+//   * the transform and the overlap-and-save dataflow against the oracle;
+//   * that every LDS exchange is a bijection inside the LDS allocation and
+//     free of bank conflicts (for 32 and for 64 four-byte banks);
+//   * that no global access leaves its buffer (NaN guard bands) and every
+//     output is written (NaN pre-fill).
+// Built as a host library (libols_emu.so); it makes no HIP runtime calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <vector>
+
+#include "ols_fft.hpp"
+#include "ols_ops.hpp"
+#include "ols_twiddle.hpp"
+
+namespace ols {
+namespace emu {
+
+using Regs = float2[16];
+
+template <int N>
+struct Group {
+  using GE = Geo<N>;
+  std::vector<float2> lds;  // with guard bands
+  float2* L;
+  static constexpr int GUARD = 4096;
+  Group() : lds(GE::LDS + 2 * GUARD) { L = lds.data() + GUARD; }
+  void poison() {
+    const float nan = std::numeric_limits<float>::quiet_NaN();
+    for (auto& v : lds) v = make_float2(nan, nan);
+  }
+  bool guards_ok() const {
+    for (int i = 0; i < GUARD; ++i) {
+      if (!std::isnan(lds[i].x) || !std::isnan(lds[lds.size() - 1 - i].x)) return false;
+    }
+    return true;
+  }
+};
+
+template <int N, int K>
+void fwd_from(std::vector<std::array<float2, 16>>& xs, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw) {
+  using GE = Geo<N>;
+  const int T = GE::WG;
+  for (int t = 0; t < T; ++t) {
+    float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
+    run_pass<N, K, false>(x, tw[t].data() + GE::lane_tw_offset(K));
+  }
+  if constexpr (K + 1 < GE::P) {
+    G.poison();
+    for (int t = 0; t < T; ++t) {
+      const int grp = t / GE::G, g = t % GE::G;
+      lds_store<N, K, K>(G.L, *reinterpret_cast<float2(*)[16]>(xs[t].data()), grp, g);
+    }
+    for (int t = 0; t < T; ++t) {
+      const int grp = t / GE::G, g = t % GE::G;
+      lds_load<N, K, K + 1>(G.L, *reinterpret_cast<float2(*)[16]>(xs[t].data()), grp, g);
+    }
+    fwd_from<N, K + 1>(xs, G, tw);
+  }
+}
+
+template <int N, int K>
+void inv_from(std::vector<std::array<float2, 16>>& xs, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw) {
+  using GE = Geo<N>;
+  const int T = GE::WG;
+  for (int t = 0; t < T; ++t) {
+    float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
+    run_pass<N, K, true>(x, tw[t].data() + GE::lane_tw_offset(K));
+  }
+  if constexpr (K > 0) {
+    G.poison();
+    for (int t = 0; t < T; ++t) {
+      const int grp = t / GE::G, g = t % GE::G;
+      lds_store<N, K - 1, K>(G.L, *reinterpret_cast<float2(*)[16]>(xs[t].data()), grp, g);
+    }
+    for (int t = 0; t < T; ++t) {
+      const int grp = t / GE::G, g = t % GE::G;
+      lds_load<N, K - 1, K - 1>(G.L, *reinterpret_cast<float2(*)[16]>(xs[t].data()), grp, g);
+    }
+    inv_from<N, K - 1>(xs, G, tw);
+  }
+}
+
+template <int N>
+std::vector<std::array<float2, Geo<N>::TWR>> lane_twiddles(const std::vector<float2>& table) {
+  using GE = Geo<N>;
+  std::vector<std::array<float2, GE::TWR>> tw(GE::WG);
+  for (int t = 0; t < GE::WG; ++t) {
+    float2 tmp[GE::TWR];
+    load_lane_twiddles<N>(tmp, table.data(), t % GE::G);
+    for (int i = 0; i < GE::TWR; ++i) tw[t][i] = tmp[i];
+  }
+  return tw;
+}
+
+// Filter spectra in kernel order F[K][16][G] (as the device plan stores them).
+template <int N>
+std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<float2>& table, bool* guards) {
+  using GE = Geo<N>;
+  auto tw = lane_twiddles<N>(table);
+  std::vector<float2> F((size_t)K * N);
+  Group<N> G;
+  G.poison();
+  std::vector<std::array<float2, 16>> xs(GE::WG);
+  const int blocks = (K + GE::SEGS - 1) / GE::SEGS;
+  for (int b = 0; b < blocks; ++b) {
+    for (int t = 0; t < GE::WG; ++t) {
+      const int grp = t / GE::G, g = t % GE::G;
+      const int r = b * GE::SEGS + grp;
+      const bool valid = r < K;
+      load_filter<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), h + (int64_t)(valid ? r : 0) * M, M, valid, g);
+    }
+    fwd_from<N, 0>(xs, G, tw);
+    for (int t = 0; t < GE::WG; ++t) {
+      const int grp = t / GE::G, g = t % GE::G;
+      const int r = b * GE::SEGS + grp;
+      if (r < K) store_spectrum<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), F.data(), r, g, 1.0f / (float)N);
+    }
+  }
+  if (guards) *guards = G.guards_ok();
+  return F;
+}
+
+template <int N>
+int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y) {
+  using GE = Geo<N>;
+  const std::vector<float2> table = build_twiddles<N>();
+  bool guards = true;
+  const std::vector<float2> F = spectra<N>(h, K, M, table, &guards);
+  if (!guards) return 2;
+  auto tw = lane_twiddles<N>(table);
+  const int64_t nseg = (Ns + H - 1) / H;
+  const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
+  const int64_t U = ntiles * K;
+  if (grid > U) grid = (int)U;
+  Group<N> G;
+  G.poison();
+  std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
+  float2 f[16];
+  for (int b = 0; b < grid; ++b) {
+    const int64_t u0 = U * b / grid, u1 = U * (b + 1) / grid;
+    if (u0 >= u1) continue;
+    int64_t tile = u0 / K;
+    int r = (int)(u0 - tile * K);
+    auto forward_tile = [&]() {
+      for (int t = 0; t < GE::WG; ++t) {
+        const int grp = t / GE::G, g = t % GE::G;
+        const int64_t seg = tile * GE::SEGS + grp;
+        load_segment<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), s, Ns, seg * H - D, g);
+      }
+      fwd_from<N, 0>(xs, G, tw);
+      A = xs;
+    };
+    forward_tile();
+    for (int64_t u = u0; u < u1; ++u) {
+      if (r == K) {
+        r = 0;
+        ++tile;
+        forward_tile();
+      }
+      for (int t = 0; t < GE::WG; ++t) {
+        const int g = t % GE::G;
+        load_spectrum<N>(f, F.data(), r, g);
+        spectrum_product(*reinterpret_cast<float2(*)[16]>(xs[t].data()), *reinterpret_cast<const float2(*)[16]>(A[t].data()), f);
+      }
+      inv_from<N, GE::P - 1>(xs, G, tw);
+      for (int t = 0; t < GE::WG; ++t) {
+        const int grp = t / GE::G, g = t % GE::G;
+        const int64_t seg = tile * GE::SEGS + grp;
+        store_valid<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
+      }
+      ++r;
+    }
+  }
+  return G.guards_ok() ? 0 : 3;
+}
+
+// LDS exchange analysis for one (exchange E, pattern K) over a whole workgroup.
+template <int N, int E, int K>
+void pattern(std::map<int, int>& seen, int64_t* out, bool writer, std::vector<int>& cells) {
+  using GE = Geo<N>;
+  constexpr int RK = GE::radix(K);
+  for (int j = 0; j < GE::slots(K); ++j) {
+    for (int a = 0; a < RK; ++a) {
+      std::vector<int> addr(GE::WG);
+      for (int t = 0; t < GE::WG; ++t) {
+        const int grp = t / GE::G, g = t % GE::G;
+        addr[t] = lds_base<N, E, K>(grp, g) + lds_off<N, E, K>(j, a);
+        if (addr[t] < 0 || addr[t] >= GE::LDS) out[2]++;
+        if (addr[t] + 1 > out[3]) out[3] = addr[t] + 1;
+        if (writer) {
+          if (seen.count(addr[t])) out[4]++;
+          seen[addr[t]] = 1;
+        } else {
+          cells.push_back(addr[t]);
+        }
+      }
+      for (int lanes = 16; lanes <= 32; lanes *= 2) {
+        for (int base = 0; base < GE::WG; base += lanes) {
+          std::map<int, int> cnt;
+          int worst = 0;
+          for (int t = base; t < base + lanes; ++t) worst = std::max(worst, ++cnt[((addr[t] % lanes) + lanes) % lanes]);
+          int64_t& w = out[lanes == 16 ? 0 : 1];
+          if (worst > w) w = worst;
+        }
+      }
+    }
+  }
+}
+
+template <int N, int E>
+void exchange_report(int64_t* out) {
+  // forward direction writes pattern E, reads pattern E+1; inverse the reverse
+  std::map<int, int> w1, w2;
+  std::vector<int> r1, r2, dummy;
+  pattern<N, E, E>(w1, out, true, dummy);
+  pattern<N, E, E + 1>(w1, out, false, r1);
+  pattern<N, E, E + 1>(w2, out, true, dummy);
+  pattern<N, E, E>(w2, out, false, r2);
+  for (int a : r1)
+    if (!w1.count(a)) out[5]++;
+  for (int a : r2)
+    if (!w2.count(a)) out[5]++;
+  if ((int64_t)r1.size() != (int64_t)w1.size()) out[5]++;
+  if constexpr (E + 1 < Geo<N>::P - 1) exchange_report<N, E + 1>(out);
+}
+
+template <int N>
+void lds_report(int64_t* out) {
+  for (int i = 0; i < 8; ++i) out[i] = 0;
+  exchange_report<N, 0>(out);
+  out[6] = Geo<N>::LDS;
+  out[7] = Geo<N>::TW_TOTAL;
+}
+
+template <template <int> class F, typename... A>
+int dispatch(int N, A... a) {
+  switch (N) {
+    case 256: return F<256>::run(a...);
+    case 512: return F<512>::run(a...);
+    case 1024: return F<1024>::run(a...);
+    case 2048: return F<2048>::run(a...);
+    case 4096: return F<4096>::run(a...);
+    case 8192: return F<8192>::run(a...);
+  }
+  return -1;
+}
+
+template <int N>
+struct RunFwd {
+  static int run(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y) {
+    return forward<N>(s, Ns, h, K, M, D, H, grid, y);
+  }
+};
+template <int N>
+struct RunSpec {
+  static int run(const float2* h, int K, int M, float2* out) {
+    bool guards = true;
+    std::vector<float2> F = spectra<N>(h, K, M, build_twiddles<N>(), &guards);
+    for (int r = 0; r < K; ++r)
+      for (int reg = 0; reg < 16; ++reg)
+        for (int g = 0; g < Geo<N>::G; ++g)
+          out[(int64_t)r * N + spectrum_index<N>(g, reg)] = F[(int64_t)r * N + reg * Geo<N>::G + g];
+    return guards ? 0 : 2;
+  }
+};
+template <int N>
+struct RunLds {
+  static int run(int64_t* out) {
+    lds_report<N>(out);
+    return 0;
+  }
+};
+template <int N>
+struct RunGeo {
+  static int run(int32_t* out) {
+    using GE = Geo<N>;
+    out[0] = GE::G;
+    out[1] = GE::P;
+    out[2] = GE::R0;
+    out[3] = GE::WG;
+    out[4] = GE::SEGS;
+    out[5] = GE::LDS;
+    out[6] = GE::TWR;
+    return 0;
+  }
+};
+
+}  // namespace emu
+}  // namespace ols
+
+extern "C" {
+
+// y[K][Ns] (interleaved floats) = forward overlap-and-save through the kernel
+// dataflow.  Returns 0 on success, 2/3 if an LDS guard band was touched, -1 for
+// an unsupported N.
+int ols_emu_forward(int N, const float* s, int64_t Ns, const float* h, int K, int M, int D, int H, int grid, float* y) {
+  return ols::emu::dispatch<ols::emu::RunFwd>(N, (const float2*)s, Ns, (const float2*)h, K, M, D, H, grid, (float2*)y);
+}
+
+// Natural-order filter spectra out[K][N] = FFT_N(pad h_r) / N through the kernel dataflow.
+int ols_emu_spectra(int N, const float* h, int K, int M, float* out) {
+  return ols::emu::dispatch<ols::emu::RunSpec>(N, (const float2*)h, K, M, (float2*)out);
+}
+
+// out[0] worst bank multiplicity for 16-lane groups / 16 slots (32 banks),
+// out[1] for 32-lane groups / 32 slots (64 banks), out[2] out-of-range LDS
+// addresses, out[3] highest address + 1, out[4] double writes within one
+// exchange, out[5] reads of cells not written by the exchange, out[6] LDS
+// size (float2), out[7] twiddle table size.
+int ols_emu_lds_report(int N, int64_t* out) { return ols::emu::dispatch<ols::emu::RunLds>(N, out); }
+
+// out[0..6] = G, P, R0, WG, SEGS, LDS (float2), TWR
+int ols_emu_geometry(int N, int32_t* out) { return ols::emu::dispatch<ols::emu::RunGeo>(N, out); }
+
+}  // extern "C"

@@ -1,0 +1,456 @@
+// Fused overlap-and-save kernels for gfx950 and the C ABI declared in ols.h.
+//
+// ols_forward_kernel<N>: one persistent workgroup processes a contiguous range
+// of (segment tile, filter) work units.  A tile is SEGS consecutive segments,
+// one N-point transform per G = N/16 lanes.  When the range enters a new tile
+// the workgroup loads its segments and forward transforms them once; the
+// spectra stay in registers for every filter of the range (sec. 3.4: the
+// segment samples are reused throughout).  Each unit multiplies by one filter
+// spectrum, inverse transforms, and writes only the unaliased samples
+// (sec. 3.2, Alg. 2).  HBM sees the signal once (plus the D-sample overlaps)
+// and every output sample once.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ols.h"
+#include "ols_fft.hpp"
+#include "ols_ops.hpp"
+#include "ols_twiddle.hpp"
+
+namespace ols {
+
+// ---------------------------------------------------------------------------
+// Transform drivers (device): passes in registers, exchanges through LDS.
+// ---------------------------------------------------------------------------
+template <int N, int K>
+__device__ __forceinline__ void fwd_from(float2 (&x)[16], float2* lds, const float2* tw, int grp, int g) {
+  run_pass<N, K, false>(x, tw + Geo<N>::lane_tw_offset(K));
+  if constexpr (K + 1 < Geo<N>::P) {
+    lds_store<N, K, K>(lds, x, grp, g);
+    __syncthreads();
+    lds_load<N, K, K + 1>(lds, x, grp, g);
+    __syncthreads();
+    fwd_from<N, K + 1>(x, lds, tw, grp, g);
+  }
+}
+
+template <int N, int K>
+__device__ __forceinline__ void inv_from(float2 (&x)[16], float2* lds, const float2* tw, int grp, int g) {
+  run_pass<N, K, true>(x, tw + Geo<N>::lane_tw_offset(K));
+  if constexpr (K > 0) {
+    lds_store<N, K - 1, K>(lds, x, grp, g);
+    __syncthreads();
+    lds_load<N, K - 1, K - 1>(lds, x, grp, g);
+    __syncthreads();
+    inv_from<N, K - 1>(x, lds, tw, grp, g);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Filter spectra (plan step): F_r = FFT_N(pad(h_r)) / N in kernel order.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const float2* __restrict__ h, int K, int M,
+                                                                        float2* __restrict__ F,
+                                                                        const float2* __restrict__ twt) {
+  using GE = Geo<N>;
+  __shared__ float2 lds[GE::LDS];
+  const int tid = threadIdx.x;
+  const int grp = tid / GE::G, g = tid - grp * GE::G;
+  const int r = blockIdx.x * GE::SEGS + grp;
+  float2 tw[GE::TWR];
+  load_lane_twiddles<N>(tw, twt, g);
+  float2 x[16];
+  const bool valid = r < K;
+  load_filter<N>(x, h + (int64_t)(valid ? r : 0) * M, M, valid, g);
+  fwd_from<N, 0>(x, lds, tw, grp, g);
+  if (valid) store_spectrum<N>(x, F, r, g, 1.0f / (float)N);
+}
+
+// Natural-order copy of the spectra: out[r][k] = F[r][reg][g] with
+// k = spectrum_index(g, reg).
+template <int N>
+__global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, float2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // over K * N
+  if (i >= (int64_t)K * N) return;
+  const int r = (int)(i / N);
+  const int rem = (int)(i - (int64_t)r * N);
+  const int reg = rem / Geo<N>::G, g = rem - reg * Geo<N>::G;
+  out[(int64_t)r * N + spectrum_index<N>(g, reg)] = F[i];
+}
+
+// ---------------------------------------------------------------------------
+// Forward overlap-and-save: persistent, balanced static partition of the
+// ntiles * K work units over the grid.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const float2* __restrict__ s, int64_t Ns,
+                                                                 const float2* __restrict__ F, float2* __restrict__ y,
+                                                                 int K, int D, int H, int64_t ntiles,
+                                                                 const float2* __restrict__ twt) {
+  using GE = Geo<N>;
+  __shared__ float2 lds[GE::LDS];
+  const int tid = threadIdx.x;
+  const int grp = tid / GE::G, g = tid - grp * GE::G;
+  const int64_t U = ntiles * K;
+  const int64_t u0 = U * blockIdx.x / gridDim.x;
+  const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
+  if (u0 >= u1) return;  // uniform over the workgroup
+
+  float2 tw[GE::TWR];
+  load_lane_twiddles<N>(tw, twt, g);
+
+  int64_t tile = u0 / K;
+  int r = (int)(u0 - tile * K);
+  float2 A[16], x[16], f[16];
+
+  int64_t seg = tile * GE::SEGS + grp;
+  load_segment<N>(x, s, Ns, seg * H - D, g);
+  fwd_from<N, 0>(x, lds, tw, grp, g);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) A[i] = x[i];
+
+  for (int64_t u = u0; u < u1; ++u) {
+    if (r == K) {  // next tile: new segments, one forward transform each
+      r = 0;
+      ++tile;
+      seg = tile * GE::SEGS + grp;
+      load_segment<N>(x, s, Ns, seg * H - D, g);
+      fwd_from<N, 0>(x, lds, tw, grp, g);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) A[i] = x[i];
+    }
+    load_spectrum<N>(f, F, r, g);
+    spectrum_product(x, A, f);
+    inv_from<N, GE::P - 1>(x, lds, tw, grp, g);
+    store_valid<N>(x, y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
+    ++r;
+  }
+}
+
+// Plain copy, the known-size workload for HBM counter calibration.
+__global__ void ols_copy_kernel(float4* __restrict__ dst, const float4* __restrict__ src, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace ols
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+using namespace ols;
+
+struct ols_plan_s {
+  int K = 0, M = 0, N = 0, D = 0, H = 0;
+  int device = 0;
+  int cus = 0;
+  int grid = 0;   // persistent workgroups of the forward kernel
+  int block = 0;  // threads per workgroup
+  int segs = 0;   // segments per tile
+  float2* spectra = nullptr;
+  float2* twiddles = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ols_status_t fail(ols_status_t st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+ols_status_t hip_fail(hipError_t e, const char* what) {
+  return fail(OLS_ERROR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int default_delay(int N, int M) {
+  const int d = ((M - 1) + 15) / 16 * 16;
+  return d <= N - 1 ? d : M - 1;
+}
+
+// Approximate FFT work per valid output sample for FFT length N; used when
+// the caller passes N = 0.
+double cost_per_output(int N, int M, int K) {
+  const int D = default_delay(N, M);
+  const int H = N - D;
+  if (H < 1) return 1e300;
+  const double lg = std::log2((double)N);
+  const double per_fft = 3.2 * N * lg;
+  const double work = (K + 1.0) * per_fft + K * 4.0 * N;
+  return work / ((double)K * H);
+}
+
+template <int N>
+struct Kern {
+  using GE = Geo<N>;
+  static hipError_t spectra(const float2* h, int K, int M, float2* F, const float2* tw, hipStream_t st) {
+    const int blocks = (K + GE::SEGS - 1) / GE::SEGS;
+    hipLaunchKernelGGL(ols_filter_spectra_kernel<N>, dim3(blocks), dim3(GE::WG), 0, st, h, K, M, F, tw);
+    return hipGetLastError();
+  }
+  static hipError_t natural(const float2* F, int K, float2* out, hipStream_t st) {
+    const int64_t total = (int64_t)K * N;
+    const int threads = 256;
+    const int64_t blocks = (total + threads - 1) / threads;
+    hipLaunchKernelGGL(ols_spectra_natural_kernel<N>, dim3((unsigned)blocks), dim3(threads), 0, st, F, K, out);
+    return hipGetLastError();
+  }
+  static hipError_t forward(const ols_plan_s* p, const float2* s, int64_t Ns, float2* y, hipStream_t st) {
+    const int64_t nseg = (Ns + p->H - 1) / p->H;
+    const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
+    const int64_t units = ntiles * p->K;
+    const int64_t grid = units < p->grid ? units : p->grid;
+    hipLaunchKernelGGL(ols_forward_kernel<N>, dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra, y, p->K,
+                       p->D, p->H, ntiles, p->twiddles);
+    return hipGetLastError();
+  }
+  static hipError_t occupancy(int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_forward_kernel<N>, GE::WG, 0);
+  }
+  static std::vector<float2> twiddles() { return build_twiddles<N>(); }
+  static int block() { return GE::WG; }
+  static int segs() { return GE::SEGS; }
+};
+
+template <template <int> class F, typename... Args>
+auto dispatch(int N, Args&&... args) -> decltype(F<256>::run(args...)) {
+  switch (N) {
+    case 256: return F<256>::run(args...);
+    case 512: return F<512>::run(args...);
+    case 1024: return F<1024>::run(args...);
+    case 2048: return F<2048>::run(args...);
+    case 4096: return F<4096>::run(args...);
+    default: return F<8192>::run(args...);
+  }
+}
+
+template <int N>
+struct RunSpectra {
+  static hipError_t run(const float2* h, int K, int M, float2* F, const float2* tw, hipStream_t st) {
+    return Kern<N>::spectra(h, K, M, F, tw, st);
+  }
+};
+template <int N>
+struct RunNatural {
+  static hipError_t run(const float2* F, int K, float2* out, hipStream_t st) { return Kern<N>::natural(F, K, out, st); }
+};
+template <int N>
+struct RunForward {
+  static hipError_t run(const ols_plan_s* p, const float2* s, int64_t Ns, float2* y, hipStream_t st) {
+    return Kern<N>::forward(p, s, Ns, y, st);
+  }
+};
+template <int N>
+struct RunOccupancy {
+  static hipError_t run(int* b) { return Kern<N>::occupancy(b); }
+};
+template <int N>
+struct RunTwiddles {
+  static std::vector<float2> run() { return Kern<N>::twiddles(); }
+};
+template <int N>
+struct RunShape {
+  static int run(int which) { return which == 0 ? Kern<N>::block() : Kern<N>::segs(); }
+};
+
+bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + bn && b0 < a0 + an;
+}
+
+void destroy_plan(ols_plan_s* p) {
+  if (!p) return;
+  if (p->spectra) (void)hipFree(p->spectra);
+  if (p->twiddles) (void)hipFree(p->twiddles);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ols_status_string(ols_status_t s) {
+  switch (s) {
+    case OLS_SUCCESS: return "success";
+    case OLS_ERROR_INVALID_VALUE: return "invalid value";
+    case OLS_ERROR_UNSUPPORTED: return "unsupported";
+    case OLS_ERROR_OUT_OF_MEMORY: return "out of memory";
+    case OLS_ERROR_HIP: return "HIP runtime error";
+    case OLS_ERROR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* ols_last_error(void) { return g_last_error.c_str(); }
+
+ols_status_t ols_plan(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int32_t N, ols_stream_t stream) {
+  try {
+    if (!plan) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+    *plan = nullptr;
+    if (!h) return fail(OLS_ERROR_INVALID_VALUE, "h is NULL");
+    if (K < 1) return fail(OLS_ERROR_INVALID_VALUE, "K must be >= 1");
+    if (M < 1) return fail(OLS_ERROR_INVALID_VALUE, "M must be >= 1");
+    if (((uintptr_t)h) % 8) return fail(OLS_ERROR_INVALID_VALUE, "h must be 8-byte aligned");
+    if (N == 0) {
+      double best = 1e301;
+      for (int n = OLS_MIN_FFT_LENGTH; n <= OLS_MAX_FFT_LENGTH; n *= 2) {
+        if (n < M) continue;
+        const double c = cost_per_output(n, M, K);
+        if (c < best) { best = c; N = n; }
+      }
+      if (N == 0) return fail(OLS_ERROR_INVALID_VALUE, "filter longer than the largest FFT length");
+    }
+    if (!is_pow2(N) || N < OLS_MIN_FFT_LENGTH || N > OLS_MAX_FFT_LENGTH)
+      return fail(OLS_ERROR_UNSUPPORTED, "N must be a power of two in [256, 8192]");
+    if (M > N) return fail(OLS_ERROR_INVALID_VALUE, "M must be <= N");
+    if ((int64_t)K * N > ((int64_t)1 << 40)) return fail(OLS_ERROR_INVALID_VALUE, "K*N too large");
+
+    ols_plan_s* p = new (std::nothrow) ols_plan_s();
+    if (!p) return fail(OLS_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    p->K = K;
+    p->M = M;
+    p->N = N;
+    p->D = default_delay(N, M);
+    p->H = N - p->D;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipGetDevice"); }
+    e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipDeviceGetAttribute"); }
+    int per_cu = 0;
+    e = dispatch<RunOccupancy>(N, &per_cu);
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "occupancy query"); }
+    if (per_cu < 1) per_cu = 1;
+    p->grid = per_cu * p->cus;
+    p->block = dispatch<RunShape>(N, 0);
+    p->segs = dispatch<RunShape>(N, 1);
+
+    std::vector<float2> tw = dispatch<RunTwiddles>(N);
+    e = hipMalloc(&p->twiddles, tw.size() * sizeof(float2));
+    if (e != hipSuccess) { destroy_plan(p); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "twiddle allocation"); }
+    e = hipMalloc(&p->spectra, (size_t)K * N * sizeof(float2));
+    if (e != hipSuccess) { destroy_plan(p); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "spectra allocation"); }
+    hipStream_t st = (hipStream_t)stream;
+    e = hipMemcpyAsync(p->twiddles, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "twiddle upload"); }
+    e = dispatch<RunSpectra>(N, (const float2*)h, K, M, p->spectra, (const float2*)p->twiddles, st);
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "filter spectra launch"); }
+    e = hipStreamSynchronize(st);  // the host twiddle buffer and h are released after this
+    if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "plan synchronisation"); }
+    *plan = p;
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_plan");
+  }
+}
+
+ols_status_t ols_plan_update_filters(ols_plan_t p, const void* h, ols_stream_t stream) {
+  try {
+    if (!p || !h) return fail(OLS_ERROR_INVALID_VALUE, "NULL argument");
+    if (((uintptr_t)h) % 8) return fail(OLS_ERROR_INVALID_VALUE, "h must be 8-byte aligned");
+    hipError_t e = dispatch<RunSpectra>(p->N, (const float2*)h, p->K, p->M, p->spectra,
+                                        (const float2*)p->twiddles, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "filter spectra launch");
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_plan_update_filters");
+  }
+}
+
+ols_status_t ols_plan_set_hop(ols_plan_t p, int32_t H) {
+  if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+  const int L = p->N - p->M + 1;
+  if (H == 0) {
+    p->D = default_delay(p->N, p->M);
+    p->H = p->N - p->D;
+    return OLS_SUCCESS;
+  }
+  if (H < 1 || H > L) return fail(OLS_ERROR_INVALID_VALUE, "hop must satisfy 1 <= H <= N-M+1");
+  int D = default_delay(p->N, p->M);
+  if (D + H > p->N) D = p->N - H;
+  p->D = D;
+  p->H = H;
+  return OLS_SUCCESS;
+}
+
+ols_status_t ols_plan_get_info(ols_plan_t p, int32_t* N, int32_t* H, int32_t* D, int32_t* K, int32_t* M) {
+  if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+  if (N) *N = p->N;
+  if (H) *H = p->H;
+  if (D) *D = p->D;
+  if (K) *K = p->K;
+  if (M) *M = p->M;
+  return OLS_SUCCESS;
+}
+
+ols_status_t ols_plan_get_launch(ols_plan_t p, int32_t* grid, int32_t* block, int32_t* cus) {
+  if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+  if (grid) *grid = p->grid;
+  if (block) *block = p->block;
+  if (cus) *cus = p->cus;
+  return OLS_SUCCESS;
+}
+
+ols_status_t ols_plan_get_spectra(ols_plan_t p, void* out, ols_stream_t stream) {
+  try {
+    if (!p || !out) return fail(OLS_ERROR_INVALID_VALUE, "NULL argument");
+    if (((uintptr_t)out) % 8) return fail(OLS_ERROR_INVALID_VALUE, "out must be 8-byte aligned");
+    if (ranges_overlap(out, (size_t)p->K * p->N * 8, p->spectra, (size_t)p->K * p->N * 8))
+      return fail(OLS_ERROR_INVALID_VALUE, "out overlaps the plan");
+    hipError_t e = dispatch<RunNatural>(p->N, (const float2*)p->spectra, p->K, (float2*)out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "spectra copy launch");
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_plan_get_spectra");
+  }
+}
+
+ols_status_t ols_forward(ols_plan_t p, const void* s, int64_t Ns, void* y, ols_stream_t stream) {
+  try {
+    if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+    if (Ns < 0) return fail(OLS_ERROR_INVALID_VALUE, "N_s must be >= 0");
+    if (Ns == 0) return OLS_SUCCESS;
+    if (!s || !y) return fail(OLS_ERROR_INVALID_VALUE, "s or y is NULL");
+    if (((uintptr_t)s) % 8 || ((uintptr_t)y) % 8) return fail(OLS_ERROR_INVALID_VALUE, "s and y must be 8-byte aligned");
+    if (Ns > ((int64_t)1 << 56) / 8 / p->K) return fail(OLS_ERROR_INVALID_VALUE, "K*N_s*8 overflows");
+    if (ranges_overlap(s, (size_t)Ns * 8, y, (size_t)Ns * 8 * (size_t)p->K))
+      return fail(OLS_ERROR_INVALID_VALUE, "y overlaps s (out of place only)");
+    hipError_t e = dispatch<RunForward>(p->N, (const ols_plan_s*)p, (const float2*)s, Ns, (float2*)y,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_forward");
+  }
+}
+
+ols_status_t ols_plan_destroy(ols_plan_t p) {
+  destroy_plan(p);
+  return OLS_SUCCESS;
+}
+
+ols_status_t ols_calibration_copy(void* dst, const void* src, size_t bytes, ols_stream_t stream) {
+  if (!dst || !src) return fail(OLS_ERROR_INVALID_VALUE, "NULL argument");
+  if (bytes % 16 || ((uintptr_t)dst) % 16 || ((uintptr_t)src) % 16)
+    return fail(OLS_ERROR_INVALID_VALUE, "size and pointers must be multiples of 16");
+  if (ranges_overlap(dst, bytes, src, bytes)) return fail(OLS_ERROR_INVALID_VALUE, "ranges overlap");
+  if (bytes == 0) return OLS_SUCCESS;
+  const int64_t n = (int64_t)(bytes / 16);
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(ols_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (float4*)dst,
+                     (const float4*)src, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "copy launch");
+  return OLS_SUCCESS;
+}
+
+}  // extern "C"

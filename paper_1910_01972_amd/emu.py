@@ -1,0 +1,82 @@
+"""Host emulator of the HIP kernels (libols_emu.so): the same per-lane code run
+on the CPU, for tests of the kernel dataflow, indexing, LDS exchanges and
+bounds without a GPU.  Not a fallback: the product path never calls it."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from ._lib import EMU_PATH
+
+_emu = None
+
+
+def emu() -> ctypes.CDLL:
+    global _emu
+    if _emu is None:
+        if not os.path.exists(EMU_PATH):
+            raise ImportError(f"{EMU_PATH} is missing: build it with `python -m paper_1910_01972_amd.build`")
+        L = ctypes.CDLL(EMU_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+        L.ols_emu_forward.argtypes = [I32, P, I64, P, I32, I32, I32, I32, I32, P]
+        L.ols_emu_spectra.argtypes = [I32, P, I32, I32, P]
+        L.ols_emu_lds_report.argtypes = [I32, P]
+        L.ols_emu_geometry.argtypes = [I32, P]
+        for f in (L.ols_emu_forward, L.ols_emu_spectra, L.ols_emu_lds_report, L.ols_emu_geometry):
+            f.restype = I32
+        _emu = L
+    return _emu
+
+
+def _ptr(a: np.ndarray) -> ctypes.c_void_p:
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def geometry(N: int) -> dict:
+    out = np.zeros(7, dtype=np.int32)
+    if emu().ols_emu_geometry(N, _ptr(out)) != 0:
+        raise ValueError(N)
+    return dict(zip(("G", "P", "R0", "WG", "SEGS", "LDS", "TWR"), out.tolist()))
+
+
+def lds_report(N: int) -> dict:
+    out = np.zeros(8, dtype=np.int64)
+    if emu().ols_emu_lds_report(N, _ptr(out)) != 0:
+        raise ValueError(N)
+    keys = ("worst16", "worst32", "out_of_range", "max_addr", "double_writes", "unwritten_reads", "lds_size",
+            "twiddles")
+    return dict(zip(keys, out.tolist()))
+
+
+def spectra(h: np.ndarray, N: int) -> np.ndarray:
+    h = np.ascontiguousarray(h, dtype=np.complex64)
+    K, M = h.shape
+    out = np.zeros((K, N), dtype=np.complex64)
+    rc = emu().ols_emu_spectra(N, _ptr(h), K, M, _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"emulator returned {rc}")
+    return out
+
+
+def forward(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, guard: int = 4096):
+    """Forward OLS through the kernel dataflow.  Signal and output are placed
+    inside NaN guard bands; returns (y, s_guard_ok, y_guard_ok)."""
+    h = np.ascontiguousarray(h, dtype=np.complex64)
+    K, M = h.shape
+    Ns = int(s.shape[0])
+    nan = np.complex64(complex(np.nan, np.nan))
+    sbuf = np.full(Ns + 2 * guard, nan, dtype=np.complex64)
+    sbuf[guard:guard + Ns] = s
+    ybuf = np.full(K * Ns + 2 * guard, nan, dtype=np.complex64)
+    sp = ctypes.c_void_p(sbuf.ctypes.data + guard * 8)
+    yp = ctypes.c_void_p(ybuf.ctypes.data + guard * 8)
+    rc = emu().ols_emu_forward(N, sp, Ns, _ptr(h), K, M, D, H, grid, yp)
+    if rc != 0:
+        raise RuntimeError(f"emulator returned {rc}")
+    y = ybuf[guard:guard + K * Ns].reshape(K, Ns).copy()
+    y_guard_ok = bool(np.all(np.isnan(ybuf[:guard])) and np.all(np.isnan(ybuf[guard + K * Ns:])))
+    s_guard_ok = bool(np.all(np.isnan(sbuf[:guard])) and np.all(np.isnan(sbuf[guard + Ns:])))
+    return y, s_guard_ok, y_guard_ok

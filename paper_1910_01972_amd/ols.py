@@ -1,0 +1,129 @@
+"""Python binding of the overlap-and-save library (argument marshalling only).
+
+Paper: overlap-and-save convolution of a long signal with K short filters
+(sec. 3.2), fused into one kernel per segment tile (sec. 3.4, Alg. 2).
+PyTorch provides device memory and streams; all arithmetic runs in libols.so.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import check, lib
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_c64(t: torch.Tensor, name: str, ndim: int) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.complex64:
+        raise TypeError(f"{name} must be complex64, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU device")
+    if t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimension(s)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class OLSPlan:
+    """Filter bank h[K][M] (complex64, on the GPU) prepared for FFT length N.
+
+    N = 0 lets the library choose.  The plan owns the filter spectra.
+    """
+
+    def __init__(self, h: torch.Tensor, N: int = 0, stream=None):
+        _check_c64(h, "h", 2)
+        self._handle = ctypes.c_void_p()
+        self.K, self.M = int(h.shape[0]), int(h.shape[1])
+        self.device = h.device
+        with torch.cuda.device(h.device):
+            check(lib().ols_plan(ctypes.byref(self._handle), ctypes.c_void_p(h.data_ptr()), self.K, self.M, int(N),
+                                 _stream_handle(stream)), "ols_plan")
+
+    def __del__(self):
+        self.close()
+
+    def close(self) -> None:
+        h = getattr(self, "_handle", None)
+        if h is not None and h.value:
+            lib().ols_plan_destroy(h)
+            self._handle = ctypes.c_void_p()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._handle.value:
+            raise RuntimeError("plan has been destroyed")
+        return self._handle
+
+    def info(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(5)]
+        check(lib().ols_plan_get_info(self.handle, *[ctypes.byref(x) for x in v]), "ols_plan_get_info")
+        return dict(zip(("N", "H", "D", "K", "M"), (x.value for x in v)))
+
+    def launch(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(3)]
+        check(lib().ols_plan_get_launch(self.handle, *[ctypes.byref(x) for x in v]), "ols_plan_get_launch")
+        return dict(zip(("grid", "block", "cus"), (x.value for x in v)))
+
+    def set_hop(self, H: int) -> None:
+        check(lib().ols_plan_set_hop(self.handle, int(H)), "ols_plan_set_hop")
+
+    def update_filters(self, h: torch.Tensor, stream=None) -> None:
+        _check_c64(h, "h", 2)
+        if tuple(h.shape) != (self.K, self.M):
+            raise ValueError("filter bank shape must stay (K, M)")
+        check(lib().ols_plan_update_filters(self.handle, ctypes.c_void_p(h.data_ptr()), _stream_handle(stream)),
+              "ols_plan_update_filters")
+
+    def spectra(self, stream=None) -> torch.Tensor:
+        """Filter spectra in natural frequency order, FFT(pad h)/N, shape (K, N)."""
+        N = self.info()["N"]
+        out = torch.empty((self.K, N), dtype=torch.complex64, device=self.device)
+        check(lib().ols_plan_get_spectra(self.handle, ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+              "ols_plan_get_spectra")
+        return out
+
+    def forward(self, s: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """y[K][N_s] = eq. (1) of s with every filter (zero history)."""
+        _check_c64(s, "s", 1)
+        Ns = int(s.shape[0])
+        if y is None:
+            y = torch.empty((self.K, Ns), dtype=torch.complex64, device=s.device)
+        else:
+            _check_c64(y, "y", 2)
+            if tuple(y.shape) != (self.K, Ns):
+                raise ValueError("y must have shape (K, N_s)")
+        check(lib().ols_forward(self.handle, ctypes.c_void_p(s.data_ptr()), Ns, ctypes.c_void_p(y.data_ptr()),
+                                _stream_handle(stream)), "ols_forward")
+        return y
+
+    __call__ = forward
+
+
+def ols_conv(s: torch.Tensor, h: torch.Tensor, N: int = 0, stream=None) -> torch.Tensor:
+    """One-shot overlap-and-save convolution: y[K][N_s]."""
+    plan = OLSPlan(h, N=N, stream=stream)
+    try:
+        return plan.forward(s, stream=stream)
+    finally:
+        # the forward is stream ordered; destroying the plan frees its spectra,
+        # so wait for the kernel first
+        (stream or torch.cuda.current_stream()).synchronize()
+        plan.close()
+
+
+def calibration_copy(dst: torch.Tensor, src: torch.Tensor, stream=None) -> None:
+    """Plain device copy with the library's own kernel (HBM counter calibration)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    check(lib().ols_calibration_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                     _stream_handle(stream)), "ols_calibration_copy")

@@ -1,0 +1,112 @@
+"""The HIP kernels' per-lane code, run on the CPU by the host emulator, against
+the oracle.  Checks indexing, LDS exchanges, bounds and the OLS dataflow
+without a GPU (the GPU parity tests repeat the comparison on the device)."""
+
+import numpy as np
+import pytest
+
+from oracle import conv
+import workloads
+
+emu = pytest.importorskip("paper_1910_01972_amd.emu")
+
+NS = (256, 512, 1024, 2048, 4096, 8192)
+
+
+def _rel(y, yr):
+    return np.linalg.norm(y - yr, axis=1) / np.maximum(np.linalg.norm(yr, axis=1), 1e-300)
+
+
+def default_delay(N, M):
+    d = (M - 1 + 15) // 16 * 16
+    return d if d <= N - 1 else M - 1
+
+
+@pytest.mark.parametrize("N", NS)
+def test_lds_exchanges_conflict_free_and_bijective(N):
+    rep = emu.lds_report(N)
+    assert rep["out_of_range"] == 0
+    assert rep["double_writes"] == 0
+    assert rep["unwritten_reads"] == 0
+    assert rep["max_addr"] <= rep["lds_size"]
+    assert rep["worst16"] == 1, rep   # 32 banks x 4 B, 16 lanes per cycle for b64
+    assert rep["worst32"] == 1, rep   # 64 banks x 4 B, 32 lanes per cycle for b64
+    g = emu.geometry(N)
+    assert g["G"] * 16 == N and g["WG"] % 64 == 0 and g["LDS"] * 8 <= 160 * 1024
+
+
+@pytest.mark.parametrize("N", NS)
+def test_spectra_vs_oracle_fft(N):
+    rng = np.random.default_rng(N)
+    for M in (1, 7, N // 2, N):
+        h = (rng.standard_normal((3, M)) + 1j * rng.standard_normal((3, M))).astype(np.complex64)
+        got = emu.spectra(h, N)
+        ref = conv.fft(np.concatenate([h.astype(np.complex128), np.zeros((3, N - M))], axis=1)) / N
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert err < 2e-6, (N, M, err)
+
+
+@pytest.mark.parametrize("N", NS)
+def test_forward_vs_oracle(N):
+    s, h = workloads.make_signal_filters(3 * N + 77, 3, max(1, N // 8), seed=N + 1)
+    M = h.shape[1]
+    D = default_delay(N, M)
+    y, sg, yg = emu.forward(s, h, N, D, N - D, grid=5)
+    assert sg and yg, "guard band touched"
+    assert not np.isnan(y).any(), "output not fully written"
+    rel = _rel(y, conv.direct_conv(s, h))
+    assert np.all(rel <= 1e-5), rel
+
+
+CASES = [
+    # (Ns, K, M, N, H or None, grid)
+    (1, 1, 1, 256, None, 1),          # single sample
+    (10, 2, 40, 256, None, 3),        # Ns < M
+    (200, 1, 256, 256, None, 2),      # M = N: one valid sample per segment
+    (5000, 5, 1, 512, None, 64),      # M = 1 (pure scaling), grid > units
+    (4097, 2, 100, 1024, 57, 9),      # odd hop, D = N - H adjustments
+    (70000, 3, 33, 1024, None, 13),   # ragged tail, several tiles per workgroup
+    (9000, 4, 513, 2048, None, 1),    # one workgroup does everything
+    (12345, 2, 2048, 4096, 1, 3),     # tiny hop
+    (30000, 2, 3000, 8192, None, 4),  # long filter, N = 8192
+]
+
+
+@pytest.mark.parametrize("Ns,K,M,N,H,grid", CASES)
+def test_forward_edge_cases(Ns, K, M, N, H, grid):
+    s, h = workloads.make_signal_filters(Ns, K, M, seed=Ns + M)
+    if H is None:
+        D = default_delay(N, M)
+        H = N - D
+    else:
+        D = default_delay(N, M)
+        if D + H > N:
+            D = N - H
+    y, sg, yg = emu.forward(s, h, N, D, H, grid)
+    assert sg and yg
+    assert not np.isnan(y).any()
+    rel = _rel(y, conv.direct_conv(s, h))
+    assert np.all(rel <= 1e-5), rel
+
+
+def test_delta_filter_identity():
+    """h = delta: inverse(forward(x)) must return the signal (sec. 3.4: the
+    inverse accepts the forward's digit-reversed order)."""
+    s, _ = workloads.make_signal_filters(5000, 1, 1, seed=3)
+    h = np.zeros((2, 64), dtype=np.complex64)
+    h[0, 0] = 1
+    h[1, 5] = 1
+    y, _, _ = emu.forward(s, h, 1024, 64, 960, 4)
+    assert np.max(np.abs(y[0] - s)) < 1e-5
+    assert np.max(np.abs(y[1, 5:] - s[:-5])) < 1e-5 and np.all(np.abs(y[1, :5]) < 1e-5)
+
+
+def test_segment_size_invariance():
+    """sec. 3.2: the result does not depend on the segment length."""
+    s, h = workloads.make_signal_filters(20000, 2, 200, seed=9)
+    ys = []
+    for N in (256, 1024, 8192):
+        D = default_delay(N, 200)
+        ys.append(emu.forward(s, h, N, D, N - D, 3)[0])
+    for y in ys[1:]:
+        assert np.max(np.abs(y - ys[0])) < 1e-4
