@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="instead of the benchmark, run the library's plain copy kernel on MIB MiB "
+                         "(known byte count, for scaling HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is single-GPU", file=sys.stderr)
@@ -91,6 +94,18 @@ def main():
 
     import workloads
     from paper_1910_01972_amd.ols import OLSPlan
+
+    if args.calibrate_copy:
+        from paper_1910_01972_amd.ols import calibration_copy
+
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup + args.steps):
+            calibration_copy(dst, src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": n * 8, "launches": args.warmup + args.steps}), flush=True)
+        return
 
     wl = workloads.WORKLOADS[WORKLOAD]
     s_np, h_np = workloads.make_signal_filters(wl.Ns, wl.K, wl.M, seed=wl.seed)

@@ -27,27 +27,35 @@ namespace ols {
 // ---------------------------------------------------------------------------
 // Transform drivers (device): passes in registers, exchanges through LDS.
 // ---------------------------------------------------------------------------
+// Exchanges alternate between two LDS buffers of Geo<N>::LDS elements.  All
+// lanes of the workgroup see the same sequence of exchanges, so one barrier
+// per exchange suffices: a lane that passes the barrier of exchange n+1 knows
+// every lane has finished reading exchange n (program order), and exchange n+2
+// reuses exchange n's buffer.  `par` selects the buffer of the next exchange.
+template <int N, int E, int KW, int KR>
+__device__ __forceinline__ void exchange(float2 (&x)[16], float2* lds, int& par, int grp, int g) {
+  float2* buf = lds + (par ? Geo<N>::LDS : 0);
+  par ^= 1;
+  lds_store<N, E, KW>(buf, x, grp, g);
+  __syncthreads();
+  lds_load<N, E, KR>(buf, x, grp, g);
+}
+
 template <int N, int K>
-__device__ __forceinline__ void fwd_from(float2 (&x)[16], float2* lds, const float2* tw, int grp, int g) {
+__device__ __forceinline__ void fwd_from(float2 (&x)[16], float2* lds, int& par, const float2* tw, int grp, int g) {
   run_pass<N, K, false>(x, tw + Geo<N>::lane_tw_offset(K));
   if constexpr (K + 1 < Geo<N>::P) {
-    lds_store<N, K, K>(lds, x, grp, g);
-    __syncthreads();
-    lds_load<N, K, K + 1>(lds, x, grp, g);
-    __syncthreads();
-    fwd_from<N, K + 1>(x, lds, tw, grp, g);
+    exchange<N, K, K, K + 1>(x, lds, par, grp, g);
+    fwd_from<N, K + 1>(x, lds, par, tw, grp, g);
   }
 }
 
 template <int N, int K>
-__device__ __forceinline__ void inv_from(float2 (&x)[16], float2* lds, const float2* tw, int grp, int g) {
+__device__ __forceinline__ void inv_from(float2 (&x)[16], float2* lds, int& par, const float2* tw, int grp, int g) {
   run_pass<N, K, true>(x, tw + Geo<N>::lane_tw_offset(K));
   if constexpr (K > 0) {
-    lds_store<N, K - 1, K>(lds, x, grp, g);
-    __syncthreads();
-    lds_load<N, K - 1, K - 1>(lds, x, grp, g);
-    __syncthreads();
-    inv_from<N, K - 1>(x, lds, tw, grp, g);
+    exchange<N, K - 1, K, K - 1>(x, lds, par, grp, g);
+    inv_from<N, K - 1>(x, lds, par, tw, grp, g);
   }
 }
 
@@ -59,16 +67,17 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const fl
                                                                         float2* __restrict__ F,
                                                                         const float2* __restrict__ twt) {
   using GE = Geo<N>;
-  __shared__ float2 lds[GE::LDS];
+  __shared__ float2 lds[2 * GE::LDS];
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
   const int r = blockIdx.x * GE::SEGS + grp;
+  int par = 0;
   float2 tw[GE::TWR];
   load_lane_twiddles<N>(tw, twt, g);
   float2 x[16];
   const bool valid = r < K;
   load_filter<N>(x, h + (int64_t)(valid ? r : 0) * M, M, valid, g);
-  fwd_from<N, 0>(x, lds, tw, grp, g);
+  fwd_from<N, 0>(x, lds, par, tw, grp, g);
   if (valid) store_spectrum<N>(x, F, r, g, 1.0f / (float)N);
 }
 
@@ -94,7 +103,7 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const float2* _
                                                                  int K, int D, int H, int64_t ntiles,
                                                                  const float2* __restrict__ twt) {
   using GE = Geo<N>;
-  __shared__ float2 lds[GE::LDS];
+  __shared__ float2 lds[2 * GE::LDS];
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
   const int64_t U = ntiles * K;
@@ -107,11 +116,14 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const float2* _
 
   int64_t tile = u0 / K;
   int r = (int)(u0 - tile * K);
+  int par = 0;
   float2 A[16], x[16], f[16];
 
+  // spectrum of the first unit's filter; later ones are prefetched one unit ahead
+  load_spectrum<N>(f, F, r, g);
   int64_t seg = tile * GE::SEGS + grp;
   load_segment<N>(x, s, Ns, seg * H - D, g);
-  fwd_from<N, 0>(x, lds, tw, grp, g);
+  fwd_from<N, 0>(x, lds, par, tw, grp, g);
 #pragma unroll
   for (int i = 0; i < 16; ++i) A[i] = x[i];
 
@@ -121,13 +133,13 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const float2* _
       ++tile;
       seg = tile * GE::SEGS + grp;
       load_segment<N>(x, s, Ns, seg * H - D, g);
-      fwd_from<N, 0>(x, lds, tw, grp, g);
+      fwd_from<N, 0>(x, lds, par, tw, grp, g);
 #pragma unroll
       for (int i = 0; i < 16; ++i) A[i] = x[i];
     }
-    load_spectrum<N>(f, F, r, g);
     spectrum_product(x, A, f);
-    inv_from<N, GE::P - 1>(x, lds, tw, grp, g);
+    if (u + 1 < u1) load_spectrum<N>(f, F, r + 1 == K ? 0 : r + 1, g);  // in flight during the transform
+    inv_from<N, GE::P - 1>(x, lds, par, tw, grp, g);
     store_valid<N>(x, y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
     ++r;
   }
