@@ -49,6 +49,16 @@ struct Group {
   }
 };
 
+template <int N, int E, int KW, int KR>
+void exchange_phase(std::vector<std::array<float2, 16>>& xs, Group<N>& G) {
+  using GE = Geo<N>;
+  G.poison();
+  for (int t = 0; t < GE::WG; ++t)
+    lds_store<N, E, KW>(G.L, *reinterpret_cast<float2(*)[16]>(xs[t].data()), t / GE::G, t % GE::G);
+  for (int t = 0; t < GE::WG; ++t)
+    lds_load<N, E, KR>(G.L, *reinterpret_cast<float2(*)[16]>(xs[t].data()), t / GE::G, t % GE::G);
+}
+
 template <int N, int K>
 void fwd_from(std::vector<std::array<float2, 16>>& xs, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw) {
   using GE = Geo<N>;
@@ -77,7 +87,7 @@ void inv_from(std::vector<std::array<float2, 16>>& xs, Group<N>& G, const std::v
   const int T = GE::WG;
   for (int t = 0; t < T; ++t) {
     float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
-    run_pass<N, K, true>(x, tw[t].data() + GE::lane_tw_offset(K));
+    inverse_pass<N, K>(x, tw[t].data() + GE::lane_tw_offset(K));
   }
   if constexpr (K > 0) {
     G.poison();
@@ -148,7 +158,6 @@ int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, i
   Group<N> G;
   G.poison();
   std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
-  float2 f[16];
   for (int b = 0; b < grid; ++b) {
     const int64_t u0 = U * b / grid, u1 = U * (b + 1) / grid;
     if (u0 >= u1) continue;
@@ -172,10 +181,13 @@ int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, i
       }
       for (int t = 0; t < GE::WG; ++t) {
         const int g = t % GE::G;
-        load_spectrum<N>(f, F.data(), r, g);
-        spectrum_product(*reinterpret_cast<float2(*)[16]>(xs[t].data()), *reinterpret_cast<const float2(*)[16]>(A[t].data()), f);
+        float2 a[16];
+        for (int i = 0; i < 16; ++i) a[i] = A[t][i];
+        load_spectrum<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), F.data(), r, g);
+        product_pass<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), a);
       }
-      inv_from<N, GE::P - 1>(xs, G, tw);
+      exchange_phase<N, GE::P - 2, GE::P - 1, GE::P - 2>(xs, G);
+      inv_from<N, GE::P - 2>(xs, G, tw);
       for (int t = 0; t < GE::WG; ++t) {
         const int grp = t / GE::G, g = t % GE::G;
         const int64_t seg = tile * GE::SEGS + grp;

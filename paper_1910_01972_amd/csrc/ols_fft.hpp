@@ -36,6 +36,26 @@ namespace ols {
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
 
+// Declares a value that is equal in every lane of the wave as uniform, so the
+// compiler keeps it (and what is derived from it) in scalar registers.  Only
+// call it on values that really are wave-uniform.
+OLS_HD int64_t wave_uniform64(int64_t v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+#else
+  return v;
+#endif
+}
+
+// A pointer that is the same in every lane of the wave, kept in scalar
+// registers: accesses become scalar base + per-lane 32-bit offset.
+template <class T>
+OLS_HD T* wave_uniform_ptr(T* p) {
+  return (T*)(intptr_t)wave_uniform64((int64_t)(intptr_t)p);
+}
+
 // ---------------------------------------------------------------------------
 // Compile-time geometry of one N-point transform.
 // ---------------------------------------------------------------------------
@@ -226,6 +246,179 @@ OLS_HD void dft(float2* v) {
   else if constexpr (RADIX == 8) dft8<INV>(v);
   else if constexpr (RADIX == 16) dft16<INV>(v);
   else static_assert(RADIX == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------------------
+// Inverse DFTs whose inputs are first multiplied by per-input factors c[i]
+// (the conjugate twiddles of an inverse pass, or the filter spectrum in the
+// point-wise product).  Each multiplication is fused into the first radix-2
+// level with FMAs: t0 = p0 + v2*c2 (two FMAs per component) and
+// t1 = 2*p0 - t0 (one FMA per component), instead of a separate complex
+// multiply followed by an add and a subtract.  CJ selects v*conj(c).
+// ---------------------------------------------------------------------------
+template <bool CJ>
+OLS_HD float2 cmul_k(float2 v, float2 c) { return CJ ? cmulc(v, c) : cmul(v, c); }
+
+// p + v*c (CJ: p + v*conj(c))
+template <bool CJ>
+OLS_HD float2 cfma(float2 v, float2 c, float2 p) {
+  return CJ ? make_float2(fmaf(v.x, c.x, fmaf(v.y, c.y, p.x)), fmaf(v.y, c.x, fmaf(-v.x, c.y, p.y)))
+            : make_float2(fmaf(v.x, c.x, fmaf(-v.y, c.y, p.x)), fmaf(v.x, c.y, fmaf(v.y, c.x, p.y)));
+}
+
+// 2a - b
+OLS_HD float2 twice_minus(float2 a, float2 b) { return make_float2(fmaf(2.f, a.x, -b.x), fmaf(2.f, a.y, -b.y)); }
+
+// Inverse DFT4 of (x0*c0, x1*c1, x2*c2, x3*c3); ONE0: c0 = 1.
+template <bool CJ, bool ONE0>
+OLS_HD void idft4_premul(float2& x0, float2& x1, float2& x2, float2& x3, float2 c0, float2 c1, float2 c2, float2 c3) {
+  const float2 p0 = ONE0 ? x0 : cmul_k<CJ>(x0, c0);
+  const float2 t0 = cfma<CJ>(x2, c2, p0);
+  const float2 t1 = twice_minus(p0, t0);
+  const float2 p1 = cmul_k<CJ>(x1, c1);
+  const float2 t2 = cfma<CJ>(x3, c3, p1);
+  const float2 t3 = mul_mi<true>(twice_minus(p1, t2));
+  x0 = cadd(t0, t2);
+  x2 = csub(t0, t2);
+  x1 = cadd(t1, t3);
+  x3 = csub(t1, t3);
+}
+
+// conj(W16^e) as a float2 (inverse-direction constant)
+template <int E>
+OLS_HD float2 w16c() {
+  constexpr float C1 = 0.92387953251128674f, S1 = 0.38268343236508978f, H = 0.70710678118654752f;
+  constexpr float tc[16] = {1.f, C1, H, S1, 0.f, -S1, -H, -C1, -1.f, -C1, -H, -S1, 0.f, S1, H, C1};
+  constexpr float ts[16] = {0.f, S1, H, C1, 1.f, C1, H, S1, 0.f, -S1, -H, -C1, -1.f, -C1, -H, -S1};
+  return make_float2(tc[E & 15], ts[E & 15]);
+}
+
+// Second radix-4 level of the inverse DFT16 for column b2: inverse DFT4 over
+// a1 of y[a1] * conj(W16^(a1*b2)), with the constant factors fused.
+template <int B2>
+OLS_HD void idft16_col(float2& y0, float2& y1, float2& y2, float2& y3) {
+  if constexpr (B2 == 0) {
+    dft4v<true>(y0, y1, y2, y3);
+  } else if constexpr (B2 == 2) {
+    // factors 1, conj W^2, conj W^4 = +i, conj W^6
+    const float2 t0 = cadd(y0, mul_mi<true>(y2));
+    const float2 t1 = csub(y0, mul_mi<true>(y2));
+    const float2 p1 = mul_w16<2, true>(y1);
+    const float2 t2 = cfma<false>(y3, w16c<6>(), p1);
+    const float2 t3 = mul_mi<true>(twice_minus(p1, t2));
+    y0 = cadd(t0, t2);
+    y2 = csub(t0, t2);
+    y1 = cadd(t1, t3);
+    y3 = csub(t1, t3);
+  } else {
+    // factors 1, conj W^B2, conj W^2B2, conj W^3B2 (none trivial for B2 = 1, 3)
+    const float2 t0 = cfma<false>(y2, w16c<2 * B2>(), y0);
+    const float2 t1 = twice_minus(y0, t0);
+    const float2 p1 = mul_w16<B2, true>(y1);
+    const float2 t2 = cfma<false>(y3, w16c<3 * B2>(), p1);
+    const float2 t3 = mul_mi<true>(twice_minus(p1, t2));
+    y0 = cadd(t0, t2);
+    y2 = csub(t0, t2);
+    y1 = cadd(t1, t3);
+    y3 = csub(t1, t3);
+  }
+}
+
+// Inverse DFT16 of v[i]*c[i] (CJ: v[i]*conj(c[i])); ONE0: c[0] = 1.
+template <bool CJ, bool ONE0>
+OLS_HD void idft16_premul(float2* v, const float2* c) {
+  float2 y[4][4];
+#pragma unroll
+  for (int a1 = 0; a1 < 4; ++a1) {
+    y[a1][0] = v[a1];
+    y[a1][1] = v[a1 + 4];
+    y[a1][2] = v[a1 + 8];
+    y[a1][3] = v[a1 + 12];
+  }
+  idft4_premul<CJ, ONE0>(y[0][0], y[0][1], y[0][2], y[0][3], c[0], c[4], c[8], c[12]);
+  idft4_premul<CJ, false>(y[1][0], y[1][1], y[1][2], y[1][3], c[1], c[5], c[9], c[13]);
+  idft4_premul<CJ, false>(y[2][0], y[2][1], y[2][2], y[2][3], c[2], c[6], c[10], c[14]);
+  idft4_premul<CJ, false>(y[3][0], y[3][1], y[3][2], y[3][3], c[3], c[7], c[11], c[15]);
+  idft16_col<0>(y[0][0], y[1][0], y[2][0], y[3][0]);
+  idft16_col<1>(y[0][1], y[1][1], y[2][1], y[3][1]);
+  idft16_col<2>(y[0][2], y[1][2], y[2][2], y[3][2]);
+  idft16_col<3>(y[0][3], y[1][3], y[2][3], y[3][3]);
+#pragma unroll
+  for (int b2 = 0; b2 < 4; ++b2) {
+    v[b2] = y[0][b2];
+    v[b2 + 4] = y[1][b2];
+    v[b2 + 8] = y[2][b2];
+    v[b2 + 12] = y[3][b2];
+  }
+}
+
+// Inverse DFT8 of v[i]*c[i]; a = a1 + 2 a2, b = b2 + 4 b1.
+template <bool CJ, bool ONE0>
+OLS_HD void idft8_premul(float2* v, const float2* c) {
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  idft4_premul<CJ, ONE0>(e0, e1, e2, e3, c[0], c[2], c[4], c[6]);
+  idft4_premul<CJ, false>(o0, o1, o2, o3, c[1], c[3], c[5], c[7]);
+  // X[b2] = e[b2] + o[b2] conj(W8^b2), X[b2+4] = e[b2] - o[b2] conj(W8^b2)
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cfma<false>(o1, w16c<2>(), e1);
+  v[5] = twice_minus(e1, v[1]);
+  const float2 o2t = mul_mi<true>(o2);
+  v[2] = cadd(e2, o2t);
+  v[6] = csub(e2, o2t);
+  v[3] = cfma<false>(o3, w16c<6>(), e3);
+  v[7] = twice_minus(e3, v[3]);
+}
+
+template <bool CJ, bool ONE0>
+OLS_HD void idft4_premul_arr(float2* v, const float2* c) {
+  idft4_premul<CJ, ONE0>(v[0], v[1], v[2], v[3], c[0], c[1], c[2], c[3]);
+}
+
+template <bool CJ, bool ONE0>
+OLS_HD void idft2_premul(float2* v, const float2* c) {
+  const float2 p0 = ONE0 ? v[0] : cmul_k<CJ>(v[0], c[0]);
+  v[0] = cfma<CJ>(v[1], c[1], p0);
+  v[1] = twice_minus(p0, v[0]);
+}
+
+template <int RADIX, bool CJ, bool ONE0>
+OLS_HD void idft_premul(float2* v, const float2* c) {
+  if constexpr (RADIX == 2) idft2_premul<CJ, ONE0>(v, c);
+  else if constexpr (RADIX == 4) idft4_premul_arr<CJ, ONE0>(v, c);
+  else if constexpr (RADIX == 8) idft8_premul<CJ, ONE0>(v, c);
+  else if constexpr (RADIX == 16) idft16_premul<CJ, ONE0>(v, c);
+  else static_assert(RADIX == 2, "unsupported radix");
+}
+
+// Inverse pass K with its conjugate twiddles fused into the butterflies.
+template <int N, int K>
+OLS_HD void inverse_pass(float2 (&x)[16], const float2* tw) {
+  using GE = Geo<N>;
+  constexpr int RK = GE::radix(K);
+  if constexpr (K < GE::P - 1) {
+#pragma unroll
+    for (int j = 0; j < GE::slots(K); ++j) {
+      float2 c[RK];
+      c[0] = make_float2(1.f, 0.f);
+#pragma unroll
+      for (int b = 1; b < RK; ++b) c[b] = tw[j * (RK - 1) + b - 1];
+      idft_premul<RK, true, true>(&x[j * RK], c);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < GE::slots(K); ++j) dft<RK, true>(&x[j * RK]);
+  }
+}
+
+// Point-wise product with the filter spectrum fused into the first inverse
+// pass (the last forward pass, radix 16, has no twiddles).  x holds the
+// filter spectrum on entry (the product commutes) and the pass output on exit.
+template <int N>
+OLS_HD void product_pass(float2 (&x)[16], const float2 (&A)[16]) {
+  static_assert(Geo<N>::radix(Geo<N>::P - 1) == 16, "last pass is radix 16");
+  idft16_premul<false, false>(x, A);
 }
 
 // ---------------------------------------------------------------------------

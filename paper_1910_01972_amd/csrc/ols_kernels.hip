@@ -41,6 +41,23 @@ __device__ __forceinline__ void exchange(float2 (&x)[16], float2* lds, int& par,
   lds_load<N, E, KR>(buf, x, grp, g);
 }
 
+// NF independent transforms exchanged together: one buffer each, written
+// before one barrier and read after it; the second barrier protects the
+// buffers from the next exchange's writes.
+template <int N, int NF, int E, int KW, int KR>
+__device__ __forceinline__ void exchange_nf(float2 (&x)[NF][16], float2* lds, int& par, int grp, int g) {
+  if constexpr (NF == 1) {
+    exchange<N, E, KW, KR>(x[0], lds, par, grp, g);
+  } else {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) lds_store<N, E, KW>(lds + f * Geo<N>::LDS, x[f], grp, g);
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < NF; ++f) lds_load<N, E, KR>(lds + f * Geo<N>::LDS, x[f], grp, g);
+    __syncthreads();
+  }
+}
+
 template <int N, int K>
 __device__ __forceinline__ void fwd_from(float2 (&x)[16], float2* lds, int& par, const float2* tw, int grp, int g) {
   run_pass<N, K, false>(x, tw + Geo<N>::lane_tw_offset(K));
@@ -52,11 +69,35 @@ __device__ __forceinline__ void fwd_from(float2 (&x)[16], float2* lds, int& par,
 
 template <int N, int K>
 __device__ __forceinline__ void inv_from(float2 (&x)[16], float2* lds, int& par, const float2* tw, int grp, int g) {
-  run_pass<N, K, true>(x, tw + Geo<N>::lane_tw_offset(K));
+  inverse_pass<N, K>(x, tw + Geo<N>::lane_tw_offset(K));
   if constexpr (K > 0) {
     exchange<N, K - 1, K, K - 1>(x, lds, par, grp, g);
     inv_from<N, K - 1>(x, lds, par, tw, grp, g);
   }
+}
+
+template <int N, int NF, int K>
+__device__ __forceinline__ void inv_from_nf(float2 (&x)[NF][16], float2* lds, int& par, const float2* tw, int grp,
+                                            int g) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f) inverse_pass<N, K>(x[f], tw + Geo<N>::lane_tw_offset(K));
+  if constexpr (K > 0) {
+    exchange_nf<N, NF, K - 1, K, K - 1>(x, lds, par, grp, g);
+    inv_from_nf<N, NF, K - 1>(x, lds, par, tw, grp, g);
+  }
+}
+
+// x[f] holds a filter spectrum on entry and the inverse FFT of A * spectrum
+// (natural order) on exit, for NF filters at once; the product is fused into
+// the first inverse pass.
+template <int N, int NF>
+__device__ __forceinline__ void inverse_of_products(float2 (&x)[NF][16], const float2 (&A)[16], float2* lds,
+                                                    int& par, const float2* tw, int grp, int g) {
+  constexpr int P = Geo<N>::P;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) product_pass<N>(x[f], A);
+  exchange_nf<N, NF, P - 2, P - 1, P - 2>(x, lds, par, grp, g);
+  inv_from_nf<N, NF, P - 2>(x, lds, par, tw, grp, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -95,18 +136,29 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
 
 // ---------------------------------------------------------------------------
 // Forward overlap-and-save: persistent, balanced static partition of the
-// ntiles * K work units over the grid.
+// ntiles * ceil(K / NF) work units over the grid.  A unit is one tile of
+// segments and NF consecutive filters, whose NF inverse transforms run
+// interleaved (independent instruction streams; one barrier pair per exchange
+// serves all NF).
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const float2* __restrict__ s, int64_t Ns,
-                                                                 const float2* __restrict__ F, float2* __restrict__ y,
-                                                                 int K, int D, int H, int64_t ntiles,
-                                                                 const float2* __restrict__ twt) {
+#ifndef OLS_WAVES
+#define OLS_WAVES 0
+#endif
+template <int N, int NF>
+__global__ __launch_bounds__(Geo<N>::WG)
+#if OLS_WAVES
+__attribute__((amdgpu_waves_per_eu(OLS_WAVES, OLS_WAVES)))
+#endif
+void ols_forward_kernel(const float2* __restrict__ s, int64_t Ns, const float2* __restrict__ F,
+                        float2* __restrict__ y, int K, int D, int H, int64_t ntiles,
+                        const float2* __restrict__ twt) {
   using GE = Geo<N>;
-  __shared__ float2 lds[2 * GE::LDS];
+  constexpr int BUFS = NF == 1 ? 2 : NF;
+  __shared__ float2 lds[BUFS * GE::LDS];
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
-  const int64_t U = ntiles * K;
+  const int KG = (K + NF - 1) / NF;  // filter groups
+  const int64_t U = ntiles * KG;
   const int64_t u0 = U * blockIdx.x / gridDim.x;
   const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
   if (u0 >= u1) return;  // uniform over the workgroup
@@ -114,34 +166,48 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const float2* _
   float2 tw[GE::TWR];
   load_lane_twiddles<N>(tw, twt, g);
 
-  int64_t tile = u0 / K;
-  int r = (int)(u0 - tile * K);
+  int64_t tile = u0 / KG;
+  int rg = (int)(u0 - tile * KG);
   int par = 0;
-  float2 A[16], x[16], f[16];
+  float2 A[16], x[NF][16];
 
-  // spectrum of the first unit's filter; later ones are prefetched one unit ahead
-  load_spectrum<N>(f, F, r, g);
-  int64_t seg = tile * GE::SEGS + grp;
-  load_segment<N>(x, s, Ns, seg * H - D, g);
-  fwd_from<N, 0>(x, lds, par, tw, grp, g);
+  // Segment index of this lane's transform; uniform over a wave when a
+  // transform spans whole waves (G >= 64).
+  auto segment_of = [&](int64_t t) -> int64_t {
+    const int64_t sg = t * GE::SEGS + grp;
+    return GE::G >= 64 ? wave_uniform64(sg) : sg;
+  };
+
+  int64_t seg = segment_of(tile);
+  load_segment<N>(x[0], s, Ns, seg * H - D, g);
+  fwd_from<N, 0>(x[0], lds, par, tw, grp, g);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) A[i] = x[i];
+  for (int i = 0; i < 16; ++i) A[i] = x[0][i];
 
   for (int64_t u = u0; u < u1; ++u) {
-    if (r == K) {  // next tile: new segments, one forward transform each
-      r = 0;
+    if (rg == KG) {  // next tile: new segments, one forward transform each
+      rg = 0;
       ++tile;
-      seg = tile * GE::SEGS + grp;
-      load_segment<N>(x, s, Ns, seg * H - D, g);
-      fwd_from<N, 0>(x, lds, par, tw, grp, g);
+      seg = segment_of(tile);
+      load_segment<N>(x[0], s, Ns, seg * H - D, g);
+      fwd_from<N, 0>(x[0], lds, par, tw, grp, g);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) A[i] = x[i];
+      for (int i = 0; i < 16; ++i) A[i] = x[0][i];
     }
-    spectrum_product(x, A, f);
-    if (u + 1 < u1) load_spectrum<N>(f, F, r + 1 == K ? 0 : r + 1, g);  // in flight during the transform
-    inv_from<N, GE::P - 1>(x, lds, par, tw, grp, g);
-    store_valid<N>(x, y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
-    ++r;
+    // spectra of this unit's filters; filters past K (a ragged last group)
+    // reuse the last filter's spectrum and are not stored
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int r = rg * NF + f;
+      load_spectrum<N>(x[f], F, r < K ? r : K - 1, g);
+    }
+    inverse_of_products<N, NF>(x, A, lds, par, tw, grp, g);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int r = rg * NF + f;
+      if (NF == 1 || r < K) store_valid<N>(x[f], y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
+    }
+    ++rg;
   }
 }
 
@@ -165,6 +231,7 @@ struct ols_plan_s {
   int grid = 0;   // persistent workgroups of the forward kernel
   int block = 0;  // threads per workgroup
   int segs = 0;   // segments per tile
+  int nf = 1;     // filters per work unit of the forward kernel
   float2* spectra = nullptr;
   float2* twiddles = nullptr;
 };
@@ -201,9 +268,15 @@ double cost_per_output(int N, int M, int K) {
   return work / ((double)K * H);
 }
 
+// Filters per work unit: two interleaved transforms when registers allow it
+// (N <= 4096) and the filter count wastes little on a padded last group.
+int choose_nf(int N, int K) { return (N <= 4096 && (K % 2 == 0 || K >= 9)) ? 2 : 1; }
+
 template <int N>
 struct Kern {
   using GE = Geo<N>;
+  static constexpr bool HAS_NF2 = N <= 4096;
+
   static hipError_t spectra(const float2* h, int K, int M, float2* F, const float2* tw, hipStream_t st) {
     const int blocks = (K + GE::SEGS - 1) / GE::SEGS;
     hipLaunchKernelGGL(ols_filter_spectra_kernel<N>, dim3(blocks), dim3(GE::WG), 0, st, h, K, M, F, tw);
@@ -216,17 +289,28 @@ struct Kern {
     hipLaunchKernelGGL(ols_spectra_natural_kernel<N>, dim3((unsigned)blocks), dim3(threads), 0, st, F, K, out);
     return hipGetLastError();
   }
-  static hipError_t forward(const ols_plan_s* p, const float2* s, int64_t Ns, float2* y, hipStream_t st) {
+  template <int NF>
+  static hipError_t forward_nf(const ols_plan_s* p, const float2* s, int64_t Ns, float2* y, hipStream_t st) {
     const int64_t nseg = (Ns + p->H - 1) / p->H;
     const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
-    const int64_t units = ntiles * p->K;
+    const int64_t units = ntiles * ((p->K + NF - 1) / NF);
     const int64_t grid = units < p->grid ? units : p->grid;
-    hipLaunchKernelGGL(ols_forward_kernel<N>, dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra, y, p->K,
-                       p->D, p->H, ntiles, p->twiddles);
+    hipLaunchKernelGGL((ols_forward_kernel<N, NF>), dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra, y,
+                       p->K, p->D, p->H, ntiles, p->twiddles);
     return hipGetLastError();
   }
-  static hipError_t occupancy(int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_forward_kernel<N>, GE::WG, 0);
+  static hipError_t forward(const ols_plan_s* p, const float2* s, int64_t Ns, float2* y, hipStream_t st) {
+    if constexpr (HAS_NF2) {
+      if (p->nf == 2) return forward_nf<2>(p, s, Ns, y, st);
+    }
+    return forward_nf<1>(p, s, Ns, y, st);
+  }
+  static hipError_t occupancy(int nf, int* blocks_per_cu) {
+    if constexpr (HAS_NF2) {
+      if (nf == 2)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_forward_kernel<N, 2>, GE::WG, 0);
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_forward_kernel<N, 1>, GE::WG, 0);
   }
   static std::vector<float2> twiddles() { return build_twiddles<N>(); }
   static int block() { return GE::WG; }
@@ -263,7 +347,7 @@ struct RunForward {
 };
 template <int N>
 struct RunOccupancy {
-  static hipError_t run(int* b) { return Kern<N>::occupancy(b); }
+  static hipError_t run(int nf, int* b) { return Kern<N>::occupancy(nf, b); }
 };
 template <int N>
 struct RunTwiddles {
@@ -337,8 +421,9 @@ ols_status_t ols_plan(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipGetDevice"); }
     e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipDeviceGetAttribute"); }
+    p->nf = choose_nf(N, K);
     int per_cu = 0;
-    e = dispatch<RunOccupancy>(N, &per_cu);
+    e = dispatch<RunOccupancy>(N, p->nf, &per_cu);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "occupancy query"); }
     if (per_cu < 1) per_cu = 1;
     p->grid = per_cu * p->cus;

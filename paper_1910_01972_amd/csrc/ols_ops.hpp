@@ -58,9 +58,10 @@ OLS_HD void spectrum_product(float2 (&x)[16], const float2 (&A)[16], const float
 }
 
 // After the inverse transform register reg of lane g holds circular position
-// p = g + time_pos_const(reg).  Positions D .. D+H-1 are unaliased (D >= M-1,
-// sec. 3.2) and go to outputs out0 + p - D, out0 = j*H; outputs >= N_s are
-// not written.
+// p = g + time_pos_const(reg).  Positions D .. D+H-1 are unaliased
+// (D >= M-1, sec. 3.2) and go to outputs out0 + p - D, out0 = j*H; outputs
+// >= N_s are not written.  (Per-lane predicates: variants that made the
+// full/empty decision per register in scalar code measured slower.)
 template <int N>
 OLS_HD void store_valid(const float2 (&x)[16], float2* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H,
                         int g) {

@@ -122,6 +122,9 @@ SMALL = [
     (250000, 3, 129, 2048, None),
     (123457, 2, 1000, 4096, None),
     (300001, 2, 4097, 8192, None),
+    (50000, 9, 100, 1024, None),      # odd K >= 9: two filters per unit, ragged last group
+    (20001, 11, 300, 4096, 1000),
+    (33333, 6, 1, 256, None),         # even K, N = 256 (16 transforms per workgroup)
 ]
 
 
