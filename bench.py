@@ -74,6 +74,54 @@ def cpu_baseline(s, h, n_sample: int):
     }
 
 
+def fwd_bwd_measurement(steps: int, warmup: int) -> dict:
+    """Forward, backward (ds and dh) and forward+backward on the differentiable
+    workload (2^22 samples, 16 filters of 512 taps, N = 4096), timed with HIP
+    events on the launch stream, beside the plain forward."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1910_01972_amd.ols import OLSPlan
+
+    wl = workloads.WORKLOADS["grad_2p22_k16_m512"]
+    s_np, h_np = workloads.make_signal_filters(wl.Ns, wl.K, wl.M, seed=wl.seed)
+    g_np = workloads.make_grad(wl.K, wl.Ns, seed=wl.seed)
+    s = torch.from_numpy(s_np).cuda()
+    g = torch.from_numpy(g_np).cuda()
+    plan = OLSPlan(torch.from_numpy(h_np).cuda(), N=wl.N)
+    plan.reserve_backward()
+    y = torch.empty((wl.K, wl.Ns), dtype=torch.complex64, device="cuda")
+    ds = torch.empty(wl.Ns, dtype=torch.complex64, device="cuda")
+    dh = torch.empty((wl.K, wl.M), dtype=torch.complex64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    fwd = timed(lambda: plan.forward(s, y))
+    bwd = timed(lambda: plan.backward(s, g, ds=ds, dh=dh))
+    both = timed(lambda: (plan.forward(s, y), plan.backward(s, g, ds=ds, dh=dh)))
+    plan.close()
+    out = wl.K * wl.Ns
+    return {
+        "workload": wl.name, "Ns": wl.Ns, "K": wl.K, "M": wl.M, "N": wl.N,
+        "fwd_ms": fwd, "bwd_ms": bwd, "fwd_bwd_ms": both,
+        "fwd_samples_per_s": out / (fwd * 1e-3),
+        "fwd_bwd_samples_per_s": out / (both * 1e-3),
+        "bwd_over_fwd": bwd / fwd,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,12 +217,15 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "ols_forward_kernel<2048>",
+            "kernel": "ols_forward_kernel<2048, 2>",
             "kernel_ms": kernel_ms,
             "alg_bytes_per_launch": alg_bytes,
         },
     }
     plan.close()
+    del y
+    torch.cuda.empty_cache()
+    rec["fwd_bwd"] = fwd_bwd_measurement(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(s_np, h_np, args.cpu_sample)
     print(json.dumps(rec), flush=True)

@@ -122,6 +122,37 @@ ols_status_t ols_plan_get_spectra(ols_plan_t plan, void* out, ols_stream_t strea
  */
 ols_status_t ols_forward(ols_plan_t plan, const void* s, int64_t N_s, void* y, ols_stream_t stream);
 
+/*
+ * ols_backward -- adjoint of ols_forward (gradients of a real loss L with
+ * respect to the signal and the filters, given dL/dy; complex gradients in
+ * the convention dL/d(conj z), the one PyTorch uses):
+ *   ds[m]   = sum_r sum_k conj(h_r[k]) g_r[m+k]      (g_r[n] = 0 for n >= N_s)
+ *   dh_r[k] = sum_m conj(s[m]) g_r[m+k]              (m in [0, N_s))
+ * Both are computed by overlap-and-save with the plan's segment geometry: one
+ * forward transform of each gradient window serves both; the correlation
+ * uses future samples, so its aliased samples sit at the end of each segment
+ * (footnote to eq. 2).  Segment spectra are recomputed, nothing is stored
+ * from the forward call.  Partial results are summed in a fixed order
+ * (deterministic, no atomics).
+ *
+ *   s    device, complex64 [N_s] (the forward input; may be NULL if dh is NULL)
+ *   gy   device, complex64 [K][N_s], dL/dy
+ *   ds   device, complex64 [N_s] out, or NULL to skip
+ *   dh   device, complex64 [K][M] out, or NULL to skip
+ * Outputs must not overlap the inputs or each other.  N_s = 0 writes dh = 0.
+ * The first call allocates the plan's backward workspace unless
+ * ols_plan_reserve_backward was called (then no call allocates).
+ * Errors: INVALID_VALUE, OUT_OF_MEMORY (workspace), HIP.
+ */
+ols_status_t ols_backward(ols_plan_t plan, const void* s, int64_t N_s, const void* gy, void* ds, void* dh,
+                          ols_stream_t stream);
+
+/* Allocate the plan's backward workspace now (grid x 2 x SEGS x N and
+ * grid x SEGS x K x M complex64, grid = persistent workgroups), so that
+ * ols_backward never allocates.  Idempotent.  Errors: INVALID_VALUE,
+ * OUT_OF_MEMORY, HIP. */
+ols_status_t ols_plan_reserve_backward(ols_plan_t plan);
+
 /* Release a plan and its device memory (NULL is a no-op).  The caller must
  * make sure no enqueued work still uses the plan. */
 ols_status_t ols_plan_destroy(ols_plan_t plan);

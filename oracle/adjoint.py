@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["grad_signal", "grad_filters", "grad_signal_loops", "grad_filters_loops"]
+__all__ = ["grad_signal", "grad_filters", "grad_signal_at", "grad_signal_loops", "grad_filters_loops"]
 
 
 def grad_signal_loops(g, h) -> np.ndarray:
@@ -84,3 +84,24 @@ def grad_filters(g, s, M: int, chunk: int = 1 << 16) -> np.ndarray:
         n1 = min(Ns, n0 + chunk)
         dh += (g[:, n0:n1] @ win[n0:n1])[:, ::-1]
     return dh
+
+
+def grad_signal_at(g, h, idx) -> np.ndarray:
+    """ds[m] = sum_r sum_k conj(h_r[k]) g_r[m+k] at the indices idx only
+    (local: ds[m] needs g_r[m .. m+M-1]), for sampled checks of huge problems."""
+    g = np.asarray(g, dtype=np.complex128)
+    h = np.asarray(h, dtype=np.complex128)
+    idx = np.asarray(idx, dtype=np.int64).ravel()
+    K, Ns = g.shape
+    M = h.shape[1]
+    if np.any(idx < 0) or np.any(idx >= Ns):
+        raise IndexError("index out of range")
+    src = idx[:, None] + np.arange(M)[None, :]  # (n, M): g index for tap k
+    ok = src < Ns
+    src = np.minimum(src, Ns - 1)
+    out = np.zeros(idx.shape[0], dtype=np.complex128)
+    hc = np.conj(h)
+    for r in range(K):
+        vals = np.where(ok, g[r][src], 0.0)
+        out += vals @ hc[r]
+    return out

@@ -38,6 +38,8 @@ SIGNATURES = {
     "ols_plan_get_launch": (_I32, [_P, _PI32, _PI32, _PI32]),
     "ols_forward": (_I32, [_P, _P, _I64, _P, _P]),
     "ols_plan_destroy": (_I32, [_P]),
+    "ols_backward": (_I32, [_P, _P, _I64, _P, _P, _P, _P]),
+    "ols_plan_reserve_backward": (_I32, [_P]),
     "ols_status_string": (ctypes.c_char_p, [_I32]),
     "ols_last_error": (ctypes.c_char_p, []),
     "ols_calibration_copy": (_I32, [_P, _P, ctypes.c_size_t, _P]),

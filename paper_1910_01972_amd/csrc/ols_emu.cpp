@@ -199,6 +199,121 @@ int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, i
   return G.guards_ok() ? 0 : 3;
 }
 
+// Adjoint: the same unit partition, tile start/finish, split-tile fixup and
+// fixed-order dh reduction as the device kernels.
+template <int N>
+int backward(const float2* s, int64_t Ns, const float2* gy, const float2* h, int K, int M, int D, int H, int grid,
+             float2* ds, float2* dh) {
+  using GE = Geo<N>;
+  (void)D;
+  const std::vector<float2> table = build_twiddles<N>();
+  bool guards = true;
+  const std::vector<float2> F = spectra<N>(h, K, M, table, &guards);
+  if (!guards) return 2;
+  auto tw = lane_twiddles<N>(table);
+  const int64_t nseg = (Ns + H - 1) / H;
+  const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
+  const int64_t U = ntiles * K;
+  if (grid > U) grid = (int)U;
+  const int64_t P = grid;
+  std::vector<float2> ws((size_t)P * 2 * GE::SEGS * N, make_float2(0.f, 0.f));
+  std::vector<float2> part((size_t)P * GE::SEGS * K * M, make_float2(0.f, 0.f));
+  Group<N> G;
+  G.poison();
+  std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG), acc(GE::WG);
+  for (int64_t b = 0; b < P; ++b) {
+    const int64_t u0 = first_unit(U, P, b), u1 = first_unit(U, P, b + 1);
+    if (u0 >= u1) continue;
+    const int64_t t_first = u0 / K;
+    int64_t tile = t_first;
+    int r = (int)(u0 - tile * K);
+    for (int t = 0; t < GE::WG; ++t)
+      for (int rr = 0; rr < K; ++rr)
+        zero_lags<N>(part.data() + ((b * GE::SEGS + t / GE::G) * (int64_t)K + rr) * M, M, t % GE::G);
+    auto segof = [&](int t) { return tile * GE::SEGS + t / GE::G; };
+    auto start_tile = [&]() {
+      for (int t = 0; t < GE::WG; ++t)
+        load_window<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), s, Ns, segof(t) * H, H, t % GE::G);
+      fwd_from<N, 0>(xs, G, tw);
+      for (int t = 0; t < GE::WG; ++t) {
+        conj_scaled(*reinterpret_cast<float2(*)[16]>(A[t].data()), *reinterpret_cast<float2(*)[16]>(xs[t].data()),
+                    1.0f / (float)N);
+        for (int i = 0; i < 16; ++i) acc[t][i] = make_float2(0.f, 0.f);
+      }
+    };
+    auto finish_tile = [&]() {
+      xs = acc;
+      inv_from<N, GE::P - 1>(xs, G, tw);
+      const bool complete = tile * K >= u0 && (tile + 1) * K <= u1;
+      for (int t = 0; t < GE::WG; ++t) {
+        const int grp = t / GE::G, g = t % GE::G;
+        const float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
+        if (complete) {
+          store_valid<N>(x, ds, Ns, segof(t) * H, 0, H, g);
+        } else {
+          const int slot = tile == t_first ? 0 : 1;
+          store_valid<N>(x, ws.data() + ((b * 2 + slot) * GE::SEGS + grp) * (int64_t)N, (int64_t)H, 0, 0, H, g);
+        }
+      }
+    };
+    start_tile();
+    for (int64_t u = u0; u < u1; ++u) {
+      if (r == K) {
+        finish_tile();
+        r = 0;
+        ++tile;
+        start_tile();
+      }
+      for (int t = 0; t < GE::WG; ++t)
+        load_window<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), gy + (int64_t)r * Ns, Ns, segof(t) * H, N,
+                       t % GE::G);
+      fwd_from<N, 0>(xs, G, tw);
+      for (int t = 0; t < GE::WG; ++t) {
+        float2 f[16];
+        load_spectrum<N>(f, F.data(), r, t % GE::G);
+        acc_conj_product(*reinterpret_cast<float2(*)[16]>(acc[t].data()),
+                         *reinterpret_cast<float2(*)[16]>(xs[t].data()), f);
+        float2 a[16];
+        for (int i = 0; i < 16; ++i) a[i] = A[t][i];
+        product_pass<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), a);
+      }
+      exchange_phase<N, GE::P - 2, GE::P - 1, GE::P - 2>(xs, G);
+      inv_from<N, GE::P - 2>(xs, G, tw);
+      for (int t = 0; t < GE::WG; ++t)
+        add_lags<N>(part.data() + ((b * GE::SEGS + t / GE::G) * (int64_t)K + r) * M,
+                    *reinterpret_cast<float2(*)[16]>(xs[t].data()), M, t % GE::G);
+      ++r;
+    }
+    finish_tile();
+  }
+  // split-tile fixup, exactly as the device kernel
+  for (int64_t bnd = 1; bnd < P; ++bnd) {
+    const int64_t ub = first_unit(U, P, bnd);
+    if (ub % K == 0) continue;
+    const int64_t t = ub / K;
+    if (first_unit(U, P, bnd - 1) > t * K) continue;
+    const int64_t blo = owner_of_unit(U, P, t * K), bhi = owner_of_unit(U, P, (t + 1) * K - 1);
+    for (int i = 0; i < GE::SEGS * H; ++i) {
+      const int sg = i / H, p = i - sg * H;
+      const int64_t o = (t * GE::SEGS + sg) * H + p;
+      if (o >= Ns) continue;
+      float2 a = make_float2(0.f, 0.f);
+      for (int64_t bb = blo; bb <= bhi; ++bb) {
+        const int slot = first_unit(U, P, bb) / K == t ? 0 : 1;
+        a = cadd(a, ws[((bb * 2 + slot) * GE::SEGS + sg) * (int64_t)N + p]);
+      }
+      ds[o] = a;
+    }
+  }
+  const int64_t KM = (int64_t)K * M;
+  for (int64_t i = 0; i < KM; ++i) {
+    float2 a = make_float2(0.f, 0.f);
+    for (int64_t sl = 0; sl < P * GE::SEGS; ++sl) a = cadd(a, part[sl * KM + i]);
+    dh[i] = a;
+  }
+  return G.guards_ok() ? 0 : 3;
+}
+
 // LDS exchange analysis for one (exchange E, pattern K) over a whole workgroup.
 template <int N, int E, int K>
 void pattern(std::map<int, int>& seen, int64_t* out, bool writer, std::vector<int>& cells) {
@@ -277,6 +392,13 @@ struct RunFwd {
   }
 };
 template <int N>
+struct RunBwd {
+  static int run(const float2* s, int64_t Ns, const float2* gy, const float2* h, int K, int M, int D, int H, int grid,
+                 float2* ds, float2* dh) {
+    return backward<N>(s, Ns, gy, h, K, M, D, H, grid, ds, dh);
+  }
+};
+template <int N>
 struct RunSpec {
   static int run(const float2* h, int K, int M, float2* out) {
     bool guards = true;
@@ -320,6 +442,13 @@ extern "C" {
 // an unsupported N.
 int ols_emu_forward(int N, const float* s, int64_t Ns, const float* h, int K, int M, int D, int H, int grid, float* y) {
   return ols::emu::dispatch<ols::emu::RunFwd>(N, (const float2*)s, Ns, (const float2*)h, K, M, D, H, grid, (float2*)y);
+}
+
+// Adjoint through the kernel dataflow: ds[N_s], dh[K][M].
+int ols_emu_backward(int N, const float* s, int64_t Ns, const float* gy, const float* h, int K, int M, int D, int H,
+                     int grid, float* ds, float* dh) {
+  return ols::emu::dispatch<ols::emu::RunBwd>(N, (const float2*)s, Ns, (const float2*)gy, (const float2*)h, K, M, D,
+                                              H, grid, (float2*)ds, (float2*)dh);
 }
 
 // Natural-order filter spectra out[K][N] = FFT_N(pad h_r) / N through the kernel dataflow.

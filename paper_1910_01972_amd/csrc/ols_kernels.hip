@@ -211,6 +211,146 @@ void ols_forward_kernel(const float2* __restrict__ s, int64_t Ns, const float2* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of eq. (1), by overlap-and-save.  For upstream gradients g_r:
+//   ds[m]   = sum_r sum_k conj(h_r[k]) g_r[m+k]
+//   dh_r[k] = sum_m conj(s[m]) g_r[m+k]
+// Segment j's window is g_r[jH .. jH+N-1] (future samples; the aliased
+// positions are the last M-1, footnote to eq. 2).  Per segment and filter one
+// forward transform G_r serves both gradients:
+//   ds window = IFFT(sum_r conj(F_r) G_r), positions 0 .. H-1
+//   dh_r     += first M lags of IFFT(conj(S_j)/N * G_r), S_j = FFT(s[jH .. jH+H-1])
+// Units are (tile, filter) with the filter inner, split into balanced ranges.
+// A tile whose filters are split between workgroups leaves partial ds windows
+// in ws_ds (slot 0 for a range's first tile, 1 for its last); a fixup kernel
+// adds them in workgroup order.  dh lags accumulate in each workgroup's own
+// slot of part_dh ([grid][SEGS][K][M]) and are reduced in a fixed order.
+// Nothing is atomic, so the result is deterministic.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(Geo<N>::WG) void ols_backward_kernel(
+    const float2* __restrict__ s, const float2* __restrict__ gy, int64_t Ns, const float2* __restrict__ F, int K,
+    int M, int H, int64_t ntiles, const float2* __restrict__ twt, float2* __restrict__ ds,
+    float2* __restrict__ ws_ds, float2* __restrict__ part_dh, int want_ds, int want_dh) {
+  using GE = Geo<N>;
+  __shared__ float2 lds[2 * GE::LDS];
+  const int tid = threadIdx.x;
+  const int grp = tid / GE::G, g = tid - grp * GE::G;
+  const int64_t P = gridDim.x, b = blockIdx.x;
+  const int64_t U = ntiles * K;
+  const int64_t u0 = first_unit(U, P, b), u1 = first_unit(U, P, b + 1);
+  if (u0 >= u1) return;  // uniform over the workgroup
+
+  float2 tw[GE::TWR];
+  load_lane_twiddles<N>(tw, twt, g);
+  float2* part = part_dh + (b * GE::SEGS + grp) * (int64_t)K * M;
+  if (want_dh)
+    for (int r = 0; r < K; ++r) zero_lags<N>(part + (int64_t)r * M, M, g);
+
+  const int64_t t_first = u0 / K;
+  int64_t tile = t_first;
+  int r = (int)(u0 - tile * K);
+  int par = 0;
+  float2 A[16], acc[16], x[16], f[16];
+  auto segment_of = [&](int64_t t) -> int64_t {
+    const int64_t sg = t * GE::SEGS + grp;
+    return GE::G >= 64 ? wave_uniform64(sg) : sg;
+  };
+  int64_t seg = segment_of(tile);
+
+  auto start_tile = [&]() {
+    seg = segment_of(tile);
+    if (want_dh) {
+      load_window<N>(x, s, Ns, seg * H, H, g);
+      fwd_from<N, 0>(x, lds, par, tw, grp, g);
+      conj_scaled(A, x, 1.0f / (float)N);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = make_float2(0.f, 0.f);
+  };
+  auto finish_tile = [&]() {
+    if (!want_ds) return;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = acc[i];
+    inv_from<N, GE::P - 1>(x, lds, par, tw, grp, g);
+    const bool complete = tile * K >= u0 && (tile + 1) * K <= u1;
+    if (complete) {
+      store_valid<N>(x, ds, Ns, seg * H, 0, H, g);
+    } else {
+      const int slot = tile == t_first ? 0 : 1;
+      float2* w = ws_ds + ((b * 2 + slot) * GE::SEGS + grp) * (int64_t)N;
+      store_valid<N>(x, w, (int64_t)H, 0, 0, H, g);
+    }
+  };
+
+  start_tile();
+  for (int64_t u = u0; u < u1; ++u) {
+    if (r == K) {
+      finish_tile();
+      r = 0;
+      ++tile;
+      start_tile();
+    }
+    load_window<N>(x, gy + (int64_t)r * Ns, Ns, seg * H, N, g);
+    fwd_from<N, 0>(x, lds, par, tw, grp, g);
+    if (want_ds) {
+      load_spectrum<N>(f, F, r, g);
+      acc_conj_product(acc, x, f);
+    }
+    if (want_dh) {
+      product_pass<N>(x, A);
+      exchange<N, GE::P - 2, GE::P - 1, GE::P - 2>(x, lds, par, grp, g);
+      inv_from<N, GE::P - 2>(x, lds, par, tw, grp, g);
+      add_lags<N>(part + (int64_t)r * M, x, M, g);
+    }
+    ++r;
+  }
+  finish_tile();
+}
+
+// Sums the partial ds windows of tiles split between workgroups; block b-1
+// handles the boundary between workgroups b-1 and b (the first boundary
+// inside a tile does the whole tile).
+template <int N>
+__global__ void ols_ds_fixup_kernel(const float2* __restrict__ ws_ds, float2* __restrict__ ds, int64_t Ns, int K,
+                                    int H, int64_t ntiles, int64_t P) {
+  using GE = Geo<N>;
+  const int64_t b = (int64_t)blockIdx.x + 1;
+  const int64_t U = ntiles * K;
+  const int64_t ub = first_unit(U, P, b);
+  if (ub % K == 0) return;
+  const int64_t t = ub / K;
+  if (first_unit(U, P, b - 1) > t * K) return;
+  const int64_t blo = owner_of_unit(U, P, t * K), bhi = owner_of_unit(U, P, (t + 1) * K - 1);
+  for (int i = threadIdx.x; i < GE::SEGS * H; i += blockDim.x) {
+    const int sg = i / H, p = i - sg * H;
+    const int64_t o = (t * GE::SEGS + sg) * H + p;
+    if (o >= Ns) continue;
+    float2 a = make_float2(0.f, 0.f);
+    for (int64_t bb = blo; bb <= bhi; ++bb) {
+      const int slot = first_unit(U, P, bb) / K == t ? 0 : 1;
+      a = cadd(a, ws_ds[((bb * 2 + slot) * GE::SEGS + sg) * (int64_t)N + p]);
+    }
+    ds[o] = a;
+  }
+}
+
+// dh[i] = sum over workgroup slots of part[slot][i], in slot order.
+__global__ void ols_dh_reduce_kernel(const float2* __restrict__ part, int64_t nslots, int64_t KM,
+                                     float2* __restrict__ dh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= KM) return;
+  float2 a = make_float2(0.f, 0.f);
+  for (int64_t sl = 0; sl < nslots; ++sl) a = cadd(a, part[sl * KM + i]);
+  dh[i] = a;
+}
+
+// Plain fill with zero (used instead of a memset so callers may capture it).
+__global__ void ols_zero_kernel(float2* __restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = make_float2(0.f, 0.f);
+}
+
 // Plain copy, the known-size workload for HBM counter calibration.
 __global__ void ols_copy_kernel(float4* __restrict__ dst, const float4* __restrict__ src, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -232,6 +372,9 @@ struct ols_plan_s {
   int block = 0;  // threads per workgroup
   int segs = 0;   // segments per tile
   int nf = 1;     // filters per work unit of the forward kernel
+  int bwd_grid = 0;           // persistent workgroups of the adjoint kernel
+  float2* ws_ds = nullptr;    // [bwd_grid][2][SEGS][N] partial ds windows
+  float2* part_dh = nullptr;  // [bwd_grid][SEGS][K][M] dh lag partials
   float2* spectra = nullptr;
   float2* twiddles = nullptr;
 };
@@ -312,6 +455,33 @@ struct Kern {
     }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_forward_kernel<N, 1>, GE::WG, 0);
   }
+  static hipError_t bwd_occupancy(int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_backward_kernel<N>, GE::WG, 0);
+  }
+  static hipError_t backward(const ols_plan_s* p, const float2* s, const float2* gy, int64_t Ns, float2* ds,
+                             float2* dh, hipStream_t st) {
+    const int64_t nseg = (Ns + p->H - 1) / p->H;
+    const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
+    const int64_t units = ntiles * p->K;
+    const int64_t grid = units < p->bwd_grid ? units : p->bwd_grid;
+    hipLaunchKernelGGL(ols_backward_kernel<N>, dim3((unsigned)grid), dim3(GE::WG), 0, st, s, gy, Ns, p->spectra, p->K,
+                       p->M, p->H, ntiles, p->twiddles, ds, p->ws_ds, p->part_dh, ds ? 1 : 0, dh ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ds && grid > 1) {
+      hipLaunchKernelGGL(ols_ds_fixup_kernel<N>, dim3((unsigned)(grid - 1)), dim3(256), 0, st, p->ws_ds, ds, Ns, p->K,
+                         p->H, ntiles, grid);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (dh) {
+      const int64_t KM = (int64_t)p->K * p->M;
+      hipLaunchKernelGGL(ols_dh_reduce_kernel, dim3((unsigned)((KM + 255) / 256)), dim3(256), 0, st, p->part_dh,
+                         grid * GE::SEGS, KM, dh);
+      e = hipGetLastError();
+    }
+    return e;
+  }
   static std::vector<float2> twiddles() { return build_twiddles<N>(); }
   static int block() { return GE::WG; }
   static int segs() { return GE::SEGS; }
@@ -350,6 +520,17 @@ struct RunOccupancy {
   static hipError_t run(int nf, int* b) { return Kern<N>::occupancy(nf, b); }
 };
 template <int N>
+struct RunBwdOccupancy {
+  static hipError_t run(int* b) { return Kern<N>::bwd_occupancy(b); }
+};
+template <int N>
+struct RunBackward {
+  static hipError_t run(const ols_plan_s* p, const float2* s, const float2* gy, int64_t Ns, float2* ds, float2* dh,
+                        hipStream_t st) {
+    return Kern<N>::backward(p, s, gy, Ns, ds, dh, st);
+  }
+};
+template <int N>
 struct RunTwiddles {
   static std::vector<float2> run() { return Kern<N>::twiddles(); }
 };
@@ -365,6 +546,8 @@ bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
 
 void destroy_plan(ols_plan_s* p) {
   if (!p) return;
+  if (p->ws_ds) (void)hipFree(p->ws_ds);
+  if (p->part_dh) (void)hipFree(p->part_dh);
   if (p->spectra) (void)hipFree(p->spectra);
   if (p->twiddles) (void)hipFree(p->twiddles);
   delete p;
@@ -526,6 +709,71 @@ ols_status_t ols_forward(ols_plan_t p, const void* s, int64_t Ns, void* y, ols_s
     return OLS_SUCCESS;
   } catch (...) {
     return fail(OLS_ERROR_INTERNAL, "exception in ols_forward");
+  }
+}
+
+ols_status_t ols_plan_reserve_backward(ols_plan_t p) {
+  try {
+    if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+    if (p->ws_ds && p->part_dh) return OLS_SUCCESS;
+    int per_cu = 0;
+    hipError_t e = dispatch<RunBwdOccupancy>(p->N, &per_cu);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    if (per_cu < 1) per_cu = 1;
+    const int grid = per_cu * p->cus;
+    const size_t ws = (size_t)grid * 2 * p->segs * p->N * sizeof(float2);
+    const size_t part = (size_t)grid * p->segs * p->K * p->M * sizeof(float2);
+    float2 *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, ws) != hipSuccess) { (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "backward workspace"); }
+    if (hipMalloc(&b, part) != hipSuccess) {
+      (void)hipFree(a);
+      (void)hipGetLastError();
+      return fail(OLS_ERROR_OUT_OF_MEMORY, "backward workspace");
+    }
+    p->bwd_grid = grid;
+    p->ws_ds = a;
+    p->part_dh = b;
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_plan_reserve_backward");
+  }
+}
+
+ols_status_t ols_backward(ols_plan_t p, const void* s, int64_t Ns, const void* gy, void* ds, void* dh,
+                          ols_stream_t stream) {
+  try {
+    if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+    if (Ns < 0) return fail(OLS_ERROR_INVALID_VALUE, "N_s must be >= 0");
+    if (!ds && !dh) return OLS_SUCCESS;
+    if (dh && !s && Ns > 0) return fail(OLS_ERROR_INVALID_VALUE, "s is needed for dh");
+    if (Ns > 0 && !gy) return fail(OLS_ERROR_INVALID_VALUE, "gradient is NULL");
+    const uintptr_t al = (uintptr_t)s | (uintptr_t)gy | (uintptr_t)ds | (uintptr_t)dh;
+    if (al % 8) return fail(OLS_ERROR_INVALID_VALUE, "pointers must be 8-byte aligned");
+    if (Ns > ((int64_t)1 << 56) / 8 / p->K) return fail(OLS_ERROR_INVALID_VALUE, "K*N_s*8 overflows");
+    const size_t sb = (size_t)Ns * 8, gb = (size_t)Ns * 8 * p->K, hb = (size_t)p->K * p->M * 8;
+    if (ds && (ranges_overlap(ds, sb, gy, gb) || (s && ranges_overlap(ds, sb, s, sb)) || (dh && ranges_overlap(ds, sb, dh, hb))))
+      return fail(OLS_ERROR_INVALID_VALUE, "ds overlaps an input or dh");
+    if (dh && (ranges_overlap(dh, hb, gy, gb) || ranges_overlap(dh, hb, s, sb)))
+      return fail(OLS_ERROR_INVALID_VALUE, "dh overlaps an input");
+    hipStream_t st = (hipStream_t)stream;
+    if (Ns == 0) {  // empty signal: dh is zero, ds is empty
+      if (dh) {
+        hipLaunchKernelGGL(ols_zero_kernel, dim3(64), dim3(256), 0, st, (float2*)dh, (int64_t)p->K * p->M);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "zero launch");
+      }
+      return OLS_SUCCESS;
+    }
+    if (!p->ws_ds || !p->part_dh) {
+      const ols_status_t r = ols_plan_reserve_backward(p);
+      if (r != OLS_SUCCESS) return r;
+    }
+    hipError_t e = dispatch<RunBackward>(p->N, (const ols_plan_s*)p, (const float2*)s, (const float2*)gy, Ns,
+                                         (float2*)ds, (float2*)dh, st);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_backward");
   }
 }
 

@@ -75,4 +75,63 @@ OLS_HD void store_valid(const float2 (&x)[16], float2* __restrict__ yrow, int64_
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoint (gradient) helpers.  For the adjoint, segment j's window starts at
+// j*H (no delay): the correlation with conj(h) uses future samples, so the
+// aliased positions are at the end of the window and positions 0 .. H-1 are
+// exact for H <= N - M + 1 (footnote to eq. 2).
+// ---------------------------------------------------------------------------
+
+// x[reg] = src[start + p] for p = g + time_pos_const(reg) < lim and
+// start + p < N_s (start >= 0); zero elsewhere.
+template <int N>
+OLS_HD void load_window(float2 (&x)[16], const float2* __restrict__ src, int64_t Ns, int64_t start, int lim, int g) {
+  const int64_t rem = Ns - start;
+  const int hi = rem <= 0 ? 0 : (rem >= lim ? lim : (int)rem);
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int p = g + time_pos_const<N>(reg);
+    x[reg] = p < hi ? src[start + p] : make_float2(0.f, 0.f);
+  }
+}
+
+// A = conj(x) * scale
+OLS_HD void conj_scaled(float2 (&A)[16], const float2 (&x)[16], float scale) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) A[i] = make_float2(x[i].x * scale, -x[i].y * scale);
+}
+
+// acc += G * conj(F)
+OLS_HD void acc_conj_product(float2 (&acc)[16], const float2 (&G)[16], const float2 (&F)[16]) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = cfma<true>(G[i], F[i], acc[i]);
+}
+
+// Lags 0 .. M-1 of a time-domain result: part[p] += x[reg] for p < M.  Every
+// lag is always owned by the same lane, so the read-modify-write needs no
+// synchronisation.
+template <int N>
+OLS_HD void add_lags(float2* __restrict__ part, const float2 (&x)[16], int M, int g) {
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int p = g + time_pos_const<N>(reg);
+    if (p < M) part[p] = cadd(part[p], x[reg]);
+  }
+}
+
+template <int N>
+OLS_HD void zero_lags(float2* __restrict__ part, int M, int g) {
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int p = g + time_pos_const<N>(reg);
+    if (p < M) part[p] = make_float2(0.f, 0.f);
+  }
+}
+
+// Partition arithmetic shared by the persistent kernels: workgroup b of P
+// owns units [first_unit(b), first_unit(b+1)); owner(u) inverts it.
+OLS_HD int64_t first_unit(int64_t U, int64_t P, int64_t b) { return U * b / P; }
+OLS_HD int64_t owner_of_unit(int64_t U, int64_t P, int64_t u) { return ((u + 1) * P + U - 1) / U - 1; }
+
 }  // namespace ols

@@ -25,6 +25,8 @@ def emu() -> ctypes.CDLL:
         L.ols_emu_spectra.argtypes = [I32, P, I32, I32, P]
         L.ols_emu_lds_report.argtypes = [I32, P]
         L.ols_emu_geometry.argtypes = [I32, P]
+        L.ols_emu_backward.argtypes = [I32, P, I64, P, P, I32, I32, I32, I32, I32, P, P]
+        L.ols_emu_backward.restype = I32
         for f in (L.ols_emu_forward, L.ols_emu_spectra, L.ols_emu_lds_report, L.ols_emu_geometry):
             f.restype = I32
         _emu = L
@@ -80,3 +82,22 @@ def forward(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, gua
     y_guard_ok = bool(np.all(np.isnan(ybuf[:guard])) and np.all(np.isnan(ybuf[guard + K * Ns:])))
     s_guard_ok = bool(np.all(np.isnan(sbuf[:guard])) and np.all(np.isnan(sbuf[guard + Ns:])))
     return y, s_guard_ok, y_guard_ok
+
+
+def backward(s: np.ndarray, gy: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, guard: int = 4096):
+    """Adjoint through the kernel dataflow; ds is NaN-prefilled inside NaN
+    guard bands.  Returns (ds, dh, ds_guard_ok)."""
+    h = np.ascontiguousarray(h, dtype=np.complex64)
+    gy = np.ascontiguousarray(gy, dtype=np.complex64)
+    s = np.ascontiguousarray(s, dtype=np.complex64)
+    K, M = h.shape
+    Ns = int(s.shape[0])
+    nan = np.complex64(complex(np.nan, np.nan))
+    dsbuf = np.full(Ns + 2 * guard, nan, dtype=np.complex64)
+    dh = np.full((K, M), nan, dtype=np.complex64)
+    rc = emu().ols_emu_backward(N, _ptr(s), Ns, _ptr(gy), _ptr(h), K, M, D, H, grid,
+                                ctypes.c_void_p(dsbuf.ctypes.data + guard * 8), _ptr(dh))
+    if rc != 0:
+        raise RuntimeError(f"emulator returned {rc}")
+    ok = bool(np.all(np.isnan(dsbuf[:guard])) and np.all(np.isnan(dsbuf[guard + Ns:])))
+    return dsbuf[guard:guard + Ns].copy(), dh, ok

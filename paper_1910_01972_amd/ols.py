@@ -107,6 +107,66 @@ class OLSPlan:
 
     __call__ = forward
 
+    def reserve_backward(self) -> None:
+        """Allocate the backward workspace now (later backward calls allocate nothing)."""
+        check(lib().ols_plan_reserve_backward(self.handle), "ols_plan_reserve_backward")
+
+    def backward(self, s: torch.Tensor, gy: torch.Tensor, need_ds: bool = True, need_dh: bool = True,
+                 ds: torch.Tensor | None = None, dh: torch.Tensor | None = None, stream=None):
+        """Adjoint of forward: (ds [N_s], dh [K][M]) for upstream gradient gy [K][N_s]."""
+        _check_c64(s, "s", 1)
+        _check_c64(gy, "gy", 2)
+        Ns = int(s.shape[0])
+        if tuple(gy.shape) != (self.K, Ns):
+            raise ValueError("gy must have shape (K, N_s)")
+        if need_ds and ds is None:
+            ds = torch.empty(Ns, dtype=torch.complex64, device=s.device)
+        if need_dh and dh is None:
+            dh = torch.empty((self.K, self.M), dtype=torch.complex64, device=s.device)
+        p_ds = ctypes.c_void_p(ds.data_ptr()) if need_ds else ctypes.c_void_p()
+        p_dh = ctypes.c_void_p(dh.data_ptr()) if need_dh else ctypes.c_void_p()
+        check(lib().ols_backward(self.handle, ctypes.c_void_p(s.data_ptr()), Ns, ctypes.c_void_p(gy.data_ptr()),
+                                 p_ds, p_dh, _stream_handle(stream)), "ols_backward")
+        return (ds if need_ds else None), (dh if need_dh else None)
+
+
+class OLSConvFunction(torch.autograd.Function):
+    """y = s * h (eq. 1) for a bank of learnable filters; gradients by the
+    library's adjoint kernel (segment spectra recomputed, nothing stored but
+    the inputs)."""
+
+    @staticmethod
+    def forward(ctx, s, h, plan):
+        plan.update_filters(h.detach().contiguous())
+        y = plan.forward(s.detach().contiguous())
+        ctx.save_for_backward(s, h)
+        ctx.plan = plan
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        s, h = ctx.saved_tensors
+        plan = ctx.plan
+        # the plan may have seen other filters since this forward
+        plan.update_filters(h.detach().contiguous())
+        ds, dh = plan.backward(s.detach().contiguous(), gy.contiguous(), need_ds=ctx.needs_input_grad[0],
+                               need_dh=ctx.needs_input_grad[1])
+        return ds, dh, None
+
+
+class OLSConv(torch.nn.Module):
+    """K learnable complex64 filters of length M applied to a long signal by
+    overlap-and-save; output [K][N_s]."""
+
+    def __init__(self, h_init: torch.Tensor, N: int = 0):
+        super().__init__()
+        _check_c64(h_init, "h_init", 2)
+        self.h = torch.nn.Parameter(h_init.detach().clone())
+        self.plan = OLSPlan(self.h.detach(), N=N)
+
+    def forward(self, s: torch.Tensor) -> torch.Tensor:
+        return OLSConvFunction.apply(s, self.h, self.plan)
+
 
 def ols_conv(s: torch.Tensor, h: torch.Tensor, N: int = 0, stream=None) -> torch.Tensor:
     """One-shot overlap-and-save convolution: y[K][N_s]."""

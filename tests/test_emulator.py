@@ -110,3 +110,30 @@ def test_segment_size_invariance():
         ys.append(emu.forward(s, h, N, D, N - D, 3)[0])
     for y in ys[1:]:
         assert np.max(np.abs(y - ys[0])) < 1e-4
+
+
+ADJ_CASES = [
+    # (Ns, K, M, N, grid)
+    (5000, 3, 40, 256, 7),
+    (20000, 4, 100, 1024, 13),
+    (9000, 5, 513, 2048, 6),
+    (30000, 2, 300, 4096, 9),
+    (40000, 3, 1000, 8192, 5),
+    (3000, 7, 16, 512, 64),   # more workgroups than tiles: every tile split
+    (777, 2, 64, 256, 1),     # one workgroup does everything
+    (1, 1, 1, 256, 3),
+]
+
+
+@pytest.mark.parametrize("Ns,K,M,N,grid", ADJ_CASES)
+def test_adjoint_vs_oracle(Ns, K, M, N, grid):
+    from oracle import adjoint
+    s, h = workloads.make_signal_filters(Ns, K, M, seed=Ns + K)
+    g = workloads.make_grad(K, Ns, seed=Ns)
+    D = default_delay(N, M)
+    ds, dh, ok = emu.backward(s, g, h, N, D, N - D, grid)
+    assert ok and not np.isnan(ds).any() and not np.isnan(dh).any()
+    rs = adjoint.grad_signal(g, h)
+    rh = adjoint.grad_filters(g, s, M)
+    assert np.linalg.norm(ds - rs) <= 1e-5 * np.linalg.norm(rs)
+    assert np.all(np.linalg.norm(dh - rh, axis=1) <= 1e-5 * np.linalg.norm(rh, axis=1))

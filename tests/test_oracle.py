@@ -177,3 +177,34 @@ def test_workload_generator_recipe():
     big = workloads.make_signal_filters(10, 64, 1024, seed=8)[1]
     v = np.var(big.real) * 1024
     assert 0.9 < v < 1.1
+
+
+def test_adjoint_matches_torch_autograd_convention():
+    """Library cross-check: PyTorch's own complex autograd of eq. (1) (computed
+    by zero-padded FFTs in complex128) gives the oracle's adjoint for
+    L = Re sum conj(w) y, i.e. the gradient convention of ols_backward."""
+    torch = pytest.importorskip("torch")
+    torch.manual_seed(0)
+    Ns, K, M = 64, 3, 7
+    s = torch.randn(Ns, dtype=torch.complex128, requires_grad=True)
+    h = torch.randn(K, M, dtype=torch.complex128, requires_grad=True)
+    w = torch.randn(K, Ns, dtype=torch.complex128)
+    P = 128
+    Sf = torch.fft.fft(torch.nn.functional.pad(s, (0, P - Ns)))
+    Hf = torch.fft.fft(torch.nn.functional.pad(h, (0, P - M)), dim=1)
+    y = torch.fft.ifft(Sf[None, :] * Hf, dim=1)[:, :Ns]
+    (torch.conj(w) * y).real.sum().backward()
+    P_ = adjoint.grad_signal(w.numpy(), h.detach().numpy())
+    Q_ = adjoint.grad_filters(w.numpy(), s.detach().numpy(), M)
+    assert np.abs(s.grad.numpy() - P_).max() < 1e-12
+    assert np.abs(h.grad.numpy() - Q_).max() < 1e-12
+
+
+def test_grad_signal_at():
+    rng = np.random.default_rng(12)
+    g = P.rand_c(rng, 3, 500)
+    h = P.rand_c(rng, 3, 40)
+    idx = np.array([0, 1, 100, 459, 460, 461, 499])
+    P._close(adjoint.grad_signal_at(g, h, idx), adjoint.grad_signal(g, h)[idx], 1e-12, "grad_signal_at")
+    with pytest.raises(IndexError):
+        adjoint.grad_signal_at(g, h, [500])
