@@ -122,6 +122,67 @@ def fwd_bwd_measurement(steps: int, warmup: int) -> dict:
     }
 
 
+def batched_measurement(steps: int, warmup: int) -> dict:
+    """The uneven batch (256 signals, N_s log-uniform in [2^14, 2^22], K ~
+    U{1..16}, M log-uniform in [16, 1024]) as ONE persistent launch captured in
+    a hipGraph and replayed, beside the same items run as one plain launch per
+    signal."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1910_01972_amd.ols import OLSBatch, OLSPlan
+
+    shapes = workloads.batched_items()
+    items = []
+    outputs = 0
+    for Ns, K, M, seed in shapes:
+        s, h = workloads.make_signal_filters(Ns, K, M, seed=seed)
+        items.append((torch.from_numpy(s).cuda(), torch.from_numpy(h).cuda(), 0))
+        outputs += K * Ns
+    b = OLSBatch(items)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        b.run(stream=stream)
+    stream.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        b.run(stream=stream)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    graph_ms = timed(graph.replay)
+    plans = [OLSPlan(h, N=b.item(i)["N"]) for i, (s, h, _) in enumerate(items)]
+
+    def plain():
+        for p, (s, h, _), y in zip(plans, items, b.outputs):
+            p.forward(s, y)
+
+    plain_ms = timed(plain)
+    alg = sum(8.0 * K * Ns + 8.0 * Ns + 8.0 * K * M for Ns, K, M, _ in shapes)
+    info = b.info()
+    for p in plans:
+        p.close()
+    b.close()
+    del graph
+    return {
+        "workload": "uneven_batch_256", "signals": len(shapes), "output_samples": outputs,
+        "units": info["units"], "grid": info["grid"],
+        "graph_ms": graph_ms, "samples_per_s": outputs / (graph_ms * 1e-3),
+        "GBps": alg / (graph_ms * 1e-3) / 1e9,
+        "plain_per_signal_ms": plain_ms, "plain_samples_per_s": outputs / (plain_ms * 1e-3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +287,7 @@ def main():
     del y
     torch.cuda.empty_cache()
     rec["fwd_bwd"] = fwd_bwd_measurement(args.steps, args.warmup)
+    rec["batched"] = batched_measurement(max(3, args.steps // 5), 2)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(s_np, h_np, args.cpu_sample)
     print(json.dumps(rec), flush=True)

@@ -153,6 +153,58 @@ ols_status_t ols_backward(ols_plan_t plan, const void* s, int64_t N_s, const voi
  * OUT_OF_MEMORY, HIP. */
 ols_status_t ols_plan_reserve_backward(ols_plan_t plan);
 
+/*
+ * Batched uneven overlap-and-save: many signals, each with its own filter bank
+ * (K_i filters of length M_i) and FFT length, in ONE persistent kernel launch.
+ *
+ * ols_batch_plan prepares the batch (the paper's plan step -- filter spectra
+ * first, Fig. 1 / Alg. 2 -- for every item, the segment geometry of every
+ * item, and the table of work units); ols_batched then enqueues a single
+ * persistent kernel that processes every unit of every item (sec. 3.2 /
+ * Alg. 2 per item) and allocates nothing, so it can be captured in a hipGraph
+ * and replayed.  The batch keeps the item pointers: each replay reads the
+ * signals and writes the outputs named at plan time.
+ *
+ * ols_batch_item_t (host array, copied):
+ *   s    device, complex64 [N_s];  N_s >= 0
+ *   h    device, complex64 [K][M]; read during ols_batch_plan only
+ *   K, M >= 1
+ *   N    FFT length of this item: power of two in [256, 4096], or 0 for the
+ *        library's choice (cost model; the Python tuner passes measured
+ *        choices here)
+ *   y    device, complex64 [K][N_s], must not overlap s; outputs of different
+ *        items must not overlap each other (not checked)
+ * Errors: INVALID_VALUE (item number in the message), UNSUPPORTED (N, or an
+ * M needing N > 4096), OUT_OF_MEMORY, HIP.  ols_batch_plan synchronises
+ * `stream` before returning.
+ */
+#define OLS_MAX_BATCH_FFT_LENGTH 4096
+typedef struct ols_batch_s* ols_batch_t;
+typedef struct {
+  const void* s;
+  int64_t N_s;
+  const void* h;
+  int32_t K;
+  int32_t M;
+  int32_t N;
+  void* y;
+} ols_batch_item_t;
+
+ols_status_t ols_batch_plan(ols_batch_t* batch, const ols_batch_item_t* items, int32_t n, ols_stream_t stream);
+
+/* One persistent launch over all items of the batch, on `stream`.
+ * Allocates nothing; capturable.  Errors: INVALID_VALUE, HIP. */
+ols_status_t ols_batched(ols_batch_t batch, ols_stream_t stream);
+
+/* Total work units, launch grid and item count of a batch (NULL outputs skipped). */
+ols_status_t ols_batch_get_info(ols_batch_t batch, int64_t* total_units, int32_t* grid, int32_t* n);
+
+/* FFT length, hop and delay chosen for item i. */
+ols_status_t ols_batch_get_item(ols_batch_t batch, int32_t i, int32_t* N, int32_t* H, int32_t* D);
+
+/* Release a batch (NULL is a no-op). */
+ols_status_t ols_batch_destroy(ols_batch_t batch);
+
 /* Release a plan and its device memory (NULL is a no-op).  The caller must
  * make sure no enqueued work still uses the plan. */
 ols_status_t ols_plan_destroy(ols_plan_t plan);

@@ -40,10 +40,21 @@ SIGNATURES = {
     "ols_plan_destroy": (_I32, [_P]),
     "ols_backward": (_I32, [_P, _P, _I64, _P, _P, _P, _P]),
     "ols_plan_reserve_backward": (_I32, [_P]),
+    "ols_batch_plan": (_I32, [ctypes.POINTER(_P), _P, _I32, _P]),
+    "ols_batched": (_I32, [_P, _P]),
+    "ols_batch_get_info": (_I32, [_P, ctypes.POINTER(_I64), _PI32, _PI32]),
+    "ols_batch_get_item": (_I32, [_P, _I32, _PI32, _PI32, _PI32]),
+    "ols_batch_destroy": (_I32, [_P]),
     "ols_status_string": (ctypes.c_char_p, [_I32]),
     "ols_last_error": (ctypes.c_char_p, []),
     "ols_calibration_copy": (_I32, [_P, _P, ctypes.c_size_t, _P]),
 }
+
+
+class BatchItem(ctypes.Structure):
+    """ols_batch_item_t of include/ols.h."""
+    _fields_ = [("s", ctypes.c_void_p), ("N_s", ctypes.c_int64), ("h", ctypes.c_void_p), ("K", ctypes.c_int32),
+                ("M", ctypes.c_int32), ("N", ctypes.c_int32), ("y", ctypes.c_void_p)]
 
 
 class OLSError(RuntimeError):

@@ -143,6 +143,49 @@ std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<flo
   return F;
 }
 
+// Units [u0, u1) of one signal through the kernel's per-lane code (the body
+// of the device range function).
+template <int N>
+void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int K, int D, int H, int64_t u0,
+                   int64_t u1, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw) {
+  using GE = Geo<N>;
+  std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
+  int64_t tile = u0 / K;
+  int r = (int)(u0 - tile * K);
+  auto forward_tile = [&]() {
+    for (int t = 0; t < GE::WG; ++t) {
+      const int grp = t / GE::G, g = t % GE::G;
+      const int64_t seg = tile * GE::SEGS + grp;
+      load_segment<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), s, Ns, seg * H - D, g);
+    }
+    fwd_from<N, 0>(xs, G, tw);
+    A = xs;
+  };
+  forward_tile();
+  for (int64_t u = u0; u < u1; ++u) {
+    if (r == K) {
+      r = 0;
+      ++tile;
+      forward_tile();
+    }
+    for (int t = 0; t < GE::WG; ++t) {
+      const int g = t % GE::G;
+      float2 a[16];
+      for (int i = 0; i < 16; ++i) a[i] = A[t][i];
+      load_spectrum<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), F, r, g);
+      product_pass<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), a);
+    }
+    exchange_phase<N, GE::P - 2, GE::P - 1, GE::P - 2>(xs, G);
+    inv_from<N, GE::P - 2>(xs, G, tw);
+    for (int t = 0; t < GE::WG; ++t) {
+      const int grp = t / GE::G, g = t % GE::G;
+      const int64_t seg = tile * GE::SEGS + grp;
+      store_valid<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
+    }
+    ++r;
+  }
+}
+
 template <int N>
 int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y) {
   using GE = Geo<N>;
@@ -157,44 +200,9 @@ int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, i
   if (grid > U) grid = (int)U;
   Group<N> G;
   G.poison();
-  std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
   for (int b = 0; b < grid; ++b) {
-    const int64_t u0 = U * b / grid, u1 = U * (b + 1) / grid;
-    if (u0 >= u1) continue;
-    int64_t tile = u0 / K;
-    int r = (int)(u0 - tile * K);
-    auto forward_tile = [&]() {
-      for (int t = 0; t < GE::WG; ++t) {
-        const int grp = t / GE::G, g = t % GE::G;
-        const int64_t seg = tile * GE::SEGS + grp;
-        load_segment<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), s, Ns, seg * H - D, g);
-      }
-      fwd_from<N, 0>(xs, G, tw);
-      A = xs;
-    };
-    forward_tile();
-    for (int64_t u = u0; u < u1; ++u) {
-      if (r == K) {
-        r = 0;
-        ++tile;
-        forward_tile();
-      }
-      for (int t = 0; t < GE::WG; ++t) {
-        const int g = t % GE::G;
-        float2 a[16];
-        for (int i = 0; i < 16; ++i) a[i] = A[t][i];
-        load_spectrum<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), F.data(), r, g);
-        product_pass<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), a);
-      }
-      exchange_phase<N, GE::P - 2, GE::P - 1, GE::P - 2>(xs, G);
-      inv_from<N, GE::P - 2>(xs, G, tw);
-      for (int t = 0; t < GE::WG; ++t) {
-        const int grp = t / GE::G, g = t % GE::G;
-        const int64_t seg = tile * GE::SEGS + grp;
-        store_valid<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
-      }
-      ++r;
-    }
+    const int64_t u0 = first_unit(U, grid, b), u1 = first_unit(U, grid, b + 1);
+    if (u0 < u1) forward_range<N>(s, Ns, F.data(), y, K, D, H, u0, u1, G, tw);
   }
   return G.guards_ok() ? 0 : 3;
 }
@@ -313,6 +321,37 @@ int backward(const float2* s, int64_t Ns, const float2* gy, const float2* h, int
   }
   return G.guards_ok() ? 0 : 3;
 }
+
+// Batched: the same unit table, equal shares per workgroup, binary search for
+// the first item and the walk across items as the device kernel.
+struct EmuItem {
+  const float2* s;
+  float2* y;
+  std::vector<float2> F;
+  int64_t Ns, unit_begin, units;
+  int K, M, N, D, H;
+};
+
+template <int N>
+struct RangeN {
+  static int run(EmuItem* itp, int64_t a, int64_t b) {
+    EmuItem& it = *itp;
+    static thread_local Group<N>* G = nullptr;
+    if (!G) { G = new Group<N>(); G->poison(); }
+    auto tw = lane_twiddles<N>(build_twiddles<N>());
+    forward_range<N>(it.s, it.Ns, it.F.data(), it.y, it.K, it.D, it.H, a, b, *G, tw);
+    return G->guards_ok() ? 0 : 3;
+  }
+};
+template <int N>
+struct SpecN {
+  static int run(EmuItem* itp, const float2* h) {
+    EmuItem& it = *itp;
+    bool guards = true;
+    it.F = spectra<N>(h, it.K, it.M, build_twiddles<N>(), &guards);
+    return guards ? 0 : 2;
+  }
+};
 
 // LDS exchange analysis for one (exchange E, pattern K) over a whole workgroup.
 template <int N, int E, int K>
@@ -449,6 +488,52 @@ int ols_emu_backward(int N, const float* s, int64_t Ns, const float* gy, const f
                      int grid, float* ds, float* dh) {
   return ols::emu::dispatch<ols::emu::RunBwd>(N, (const float2*)s, Ns, (const float2*)gy, (const float2*)h, K, M, D,
                                               H, grid, (float2*)ds, (float2*)dh);
+}
+
+// Batched forward through the kernel dataflow.  Per item: s, y (host), N_s,
+// K, M, N (must be given, 256..4096), D, H.  grid = persistent workgroups.
+int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t* Ns, const float* const* h,
+                    const int* K, const int* M, const int* N, const int* D, const int* H, int grid) {
+  using namespace ols::emu;
+  std::vector<EmuItem> items(n);
+  int64_t units = 0;
+  for (int i = 0; i < n; ++i) {
+    EmuItem& it = items[i];
+    it.s = (const float2*)s[i];
+    it.y = (float2*)y[i];
+    it.Ns = Ns[i];
+    it.K = K[i];
+    it.M = M[i];
+    it.N = N[i];
+    it.D = D[i];
+    it.H = H[i];
+    const int segs = 4096 / it.N;
+    const int64_t nseg = (it.Ns + it.H - 1) / it.H;
+    it.unit_begin = units;
+    it.units = ((nseg + segs - 1) / segs) * it.K;
+    units += it.units;
+    if (dispatch<SpecN>(it.N, &it, (const float2*)h[i]) != 0) return 2;
+  }
+  const int64_t P = units < grid ? units : grid;
+  for (int64_t b = 0; b < P; ++b) {
+    const int64_t u0 = ols::first_unit(units, P, b), u1 = ols::first_unit(units, P, b + 1);
+    if (u0 >= u1) continue;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (items[mid].unit_begin <= u0) lo = mid; else hi = mid - 1;
+    }
+    int64_t u = u0;
+    for (int i = lo; i < n && u < u1; ++i) {
+      EmuItem& it = items[i];
+      const int64_t end = it.unit_begin + it.units;
+      if (end <= u) continue;
+      const int64_t a = u - it.unit_begin, e = (u1 < end ? u1 : end) - it.unit_begin;
+      if (dispatch<RangeN>(it.N, &it, a, e) != 0) return 3;
+      u = it.unit_begin + e;
+    }
+  }
+  return 0;
 }
 
 // Natural-order filter spectra out[K][N] = FFT_N(pad h_r) / N through the kernel dataflow.

@@ -141,34 +141,23 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
 // interleaved (independent instruction streams; one barrier pair per exchange
 // serves all NF).
 // ---------------------------------------------------------------------------
-#ifndef OLS_WAVES
-#define OLS_WAVES 0
-#endif
+// Units [u0, u1) of one signal: the body shared by the single-signal kernel
+// and the batched kernel.  `par` carries the LDS buffer parity across calls.
 template <int N, int NF>
-__global__ __launch_bounds__(Geo<N>::WG)
-#if OLS_WAVES
-__attribute__((amdgpu_waves_per_eu(OLS_WAVES, OLS_WAVES)))
-#endif
-void ols_forward_kernel(const float2* __restrict__ s, int64_t Ns, const float2* __restrict__ F,
-                        float2* __restrict__ y, int K, int D, int H, int64_t ntiles,
-                        const float2* __restrict__ twt) {
+__device__ __forceinline__ void forward_range(const float2* __restrict__ s, int64_t Ns, const float2* __restrict__ F,
+                                              float2* __restrict__ y, int K, int D, int H,
+                                              const float2* __restrict__ twt, int64_t u0, int64_t u1, float2* lds,
+                                              int& par) {
   using GE = Geo<N>;
-  constexpr int BUFS = NF == 1 ? 2 : NF;
-  __shared__ float2 lds[BUFS * GE::LDS];
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
   const int KG = (K + NF - 1) / NF;  // filter groups
-  const int64_t U = ntiles * KG;
-  const int64_t u0 = U * blockIdx.x / gridDim.x;
-  const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
-  if (u0 >= u1) return;  // uniform over the workgroup
 
   float2 tw[GE::TWR];
   load_lane_twiddles<N>(tw, twt, g);
 
   int64_t tile = u0 / KG;
   int rg = (int)(u0 - tile * KG);
-  int par = 0;
   float2 A[16], x[NF][16];
 
   // Segment index of this lane's transform; uniform over a wave when a
@@ -208,6 +197,86 @@ void ols_forward_kernel(const float2* __restrict__ s, int64_t Ns, const float2* 
       if (NF == 1 || r < K) store_valid<N>(x[f], y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
     }
     ++rg;
+  }
+}
+
+template <int N, int NF>
+__global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const float2* __restrict__ s, int64_t Ns,
+                                                                 const float2* __restrict__ F, float2* __restrict__ y,
+                                                                 int K, int D, int H, int64_t ntiles,
+                                                                 const float2* __restrict__ twt) {
+  using GE = Geo<N>;
+  constexpr int BUFS = NF == 1 ? 2 : NF;
+  __shared__ float2 lds[BUFS * GE::LDS];
+  const int64_t U = ntiles * ((K + NF - 1) / NF);
+  const int64_t u0 = first_unit(U, gridDim.x, blockIdx.x);
+  const int64_t u1 = first_unit(U, gridDim.x, blockIdx.x + 1);
+  if (u0 >= u1) return;  // uniform over the workgroup
+  int par = 0;
+  forward_range<N, NF>(s, Ns, F, y, K, D, H, twt, u0, u1, lds, par);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forward: many signals, each with its own filters (K_i, M_i), FFT
+// length N_i in {256, ..., 4096} and hop, in one persistent launch.  The
+// items' work units are numbered consecutively (item i owns
+// [unit_begin_i, unit_begin_i + units_i)); workgroup b takes an equal share
+// of all units and walks the items its share crosses, switching on each
+// item's (N, filters per unit) to the same range body as the single-signal
+// kernel.  Every N <= 4096 uses 256 threads and the same LDS footprint, so
+// one launch covers them all.
+// ---------------------------------------------------------------------------
+struct BatchItem {
+  const float2* s;
+  float2* y;
+  const float2* spectra;  // [K][N] in transform order, scaled by 1/N
+  int64_t Ns;
+  int64_t unit_begin;
+  int64_t units;
+  int32_t K, M, N, D, H, pad;
+};
+
+// One filter per unit in the batched kernel: with every N in one kernel the
+// register allocation is the maximum over all branches, and the two-filter
+// body would push it past two waves per SIMD.
+template <int N>
+__device__ __attribute__((noinline)) void batched_item_range(const BatchItem& it, const float2* twt, int64_t a,
+                                                             int64_t b, float2* lds, int& par) {
+  forward_range<N, 1>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, twt, a, b, lds, par);
+}
+
+__global__ __launch_bounds__(256) void ols_batched_kernel(const BatchItem* __restrict__ items, int nitems,
+                                                          int64_t total_units, const float2* __restrict__ tw256,
+                                                          const float2* __restrict__ tw512,
+                                                          const float2* __restrict__ tw1024,
+                                                          const float2* __restrict__ tw2048,
+                                                          const float2* __restrict__ tw4096) {
+  __shared__ float2 lds[2 * Geo<4096>::LDS];
+  static_assert(Geo<256>::LDS == Geo<4096>::LDS && Geo<2048>::LDS == Geo<4096>::LDS, "same LDS footprint");
+  const int64_t u0 = first_unit(total_units, gridDim.x, blockIdx.x);
+  const int64_t u1 = first_unit(total_units, gridDim.x, blockIdx.x + 1);
+  if (u0 >= u1) return;
+  // first item whose units reach past u0 (binary search on unit_begin)
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (items[mid].unit_begin <= u0) lo = mid; else hi = mid - 1;
+  }
+  int par = 0;
+  int64_t u = u0;
+  for (int i = lo; i < nitems && u < u1; ++i) {
+    const BatchItem it = items[i];
+    const int64_t end = it.unit_begin + it.units;
+    if (end <= u) continue;  // items without units
+    const int64_t a = u - it.unit_begin, b = (u1 < end ? u1 : end) - it.unit_begin;
+    switch (it.N) {
+      case 256: batched_item_range<256>(it, tw256, a, b, lds, par); break;
+      case 512: batched_item_range<512>(it, tw512, a, b, lds, par); break;
+      case 1024: batched_item_range<1024>(it, tw1024, a, b, lds, par); break;
+      case 2048: batched_item_range<2048>(it, tw2048, a, b, lds, par); break;
+      default: batched_item_range<4096>(it, tw4096, a, b, lds, par); break;
+    }
+    u = it.unit_begin + b;
   }
 }
 
@@ -379,6 +448,17 @@ struct ols_plan_s {
   float2* twiddles = nullptr;
 };
 
+struct ols_batch_s {
+  int n = 0;
+  int64_t total_units = 0;
+  int grid = 0;
+  int cus = 0;
+  BatchItem* items_dev = nullptr;
+  std::vector<BatchItem> items_host;
+  float2* spectra = nullptr;
+  float2* tw[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // N = 256 .. 4096
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -538,6 +618,15 @@ template <int N>
 struct RunShape {
   static int run(int which) { return which == 0 ? Kern<N>::block() : Kern<N>::segs(); }
 };
+
+void destroy_batch(ols_batch_s* b) {
+  if (!b) return;
+  if (b->items_dev) (void)hipFree(b->items_dev);
+  if (b->spectra) (void)hipFree(b->spectra);
+  for (auto* t : b->tw)
+    if (t) (void)hipFree(t);
+  delete b;
+}
 
 bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
   const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
@@ -779,6 +868,130 @@ ols_status_t ols_backward(ols_plan_t p, const void* s, int64_t Ns, const void* g
 
 ols_status_t ols_plan_destroy(ols_plan_t p) {
   destroy_plan(p);
+  return OLS_SUCCESS;
+}
+
+ols_status_t ols_batch_plan(ols_batch_t* out, const ols_batch_item_t* items, int32_t n, ols_stream_t stream) {
+  try {
+    if (!out) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL");
+    *out = nullptr;
+    if (!items || n < 1) return fail(OLS_ERROR_INVALID_VALUE, "items is NULL or n < 1");
+    ols_batch_s* b = new (std::nothrow) ols_batch_s();
+    if (!b) return fail(OLS_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    b->n = n;
+    b->items_host.resize(n);
+    size_t spec_elems = 0;
+    int64_t units = 0;
+    for (int i = 0; i < n; ++i) {
+      const ols_batch_item_t& it = items[i];
+      const std::string where = "item " + std::to_string(i) + ": ";
+      if (it.K < 1 || it.M < 1 || it.N_s < 0) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "K, M >= 1 and N_s >= 0 required"); }
+      if (!it.h || (it.N_s > 0 && (!it.s || !it.y))) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "NULL pointer"); }
+      if (((uintptr_t)it.s | (uintptr_t)it.y | (uintptr_t)it.h) % 8) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "pointers must be 8-byte aligned"); }
+      if (it.N_s > ((int64_t)1 << 56) / 8 / it.K) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "K*N_s*8 overflows"); }
+      if (it.N_s > 0 && ranges_overlap(it.s, (size_t)it.N_s * 8, it.y, (size_t)it.N_s * 8 * it.K)) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "y overlaps s"); }
+      int N = it.N;
+      if (N == 0) {
+        double best = 1e301;
+        for (int c = OLS_MIN_FFT_LENGTH; c <= OLS_MAX_BATCH_FFT_LENGTH; c *= 2) {
+          if (c < it.M) continue;
+          const double cost = cost_per_output(c, it.M, it.K);
+          if (cost < best) { best = cost; N = c; }
+        }
+        if (N == 0) { destroy_batch(b); return fail(OLS_ERROR_UNSUPPORTED, where + "filter longer than the largest batched FFT length"); }
+      }
+      if (!is_pow2(N) || N < OLS_MIN_FFT_LENGTH || N > OLS_MAX_BATCH_FFT_LENGTH) { destroy_batch(b); return fail(OLS_ERROR_UNSUPPORTED, where + "batched N must be a power of two in [256, 4096]"); }
+      if (it.M > N) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "M must be <= N"); }
+      BatchItem& d = b->items_host[i];
+      d.s = (const float2*)it.s;
+      d.y = (float2*)it.y;
+      d.Ns = it.N_s;
+      d.K = it.K;
+      d.M = it.M;
+      d.N = N;
+      d.D = default_delay(N, it.M);
+      d.H = N - d.D;
+      d.pad = 0;
+      const int segs = 4096 / N;  // transforms per 256-thread workgroup
+      const int64_t nseg = (it.N_s + d.H - 1) / d.H;
+      const int64_t ntiles = (nseg + segs - 1) / segs;
+      d.unit_begin = units;
+      d.units = ntiles * it.K;
+      units += d.units;
+      spec_elems += (size_t)it.K * N;
+    }
+    b->total_units = units;
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "hipGetDevice"); }
+    if ((e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "hipDeviceGetAttribute"); }
+    int per_cu = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ols_batched_kernel, 256, 0)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "occupancy query"); }
+    b->grid = (per_cu < 1 ? 1 : per_cu) * b->cus;
+    hipStream_t st = (hipStream_t)stream;
+    // twiddle tables for every batched N
+    std::vector<float2> tws[5] = {RunTwiddles<256>::run(), RunTwiddles<512>::run(), RunTwiddles<1024>::run(),
+                                  RunTwiddles<2048>::run(), RunTwiddles<4096>::run()};
+    for (int k = 0; k < 5; ++k) {
+      if (hipMalloc(&b->tw[k], tws[k].size() * sizeof(float2)) != hipSuccess) { destroy_batch(b); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "twiddle allocation"); }
+      if ((e = hipMemcpyAsync(b->tw[k], tws[k].data(), tws[k].size() * sizeof(float2), hipMemcpyHostToDevice, st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "twiddle upload"); }
+    }
+    if (hipMalloc(&b->spectra, spec_elems * sizeof(float2)) != hipSuccess) { destroy_batch(b); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "spectra allocation"); }
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+      BatchItem& d = b->items_host[i];
+      float2* F = b->spectra + off;
+      d.spectra = F;
+      off += (size_t)d.K * d.N;
+      const int k = ilog2(d.N) - 8;
+      e = dispatch<RunSpectra>(d.N, (const float2*)items[i].h, d.K, d.M, F, (const float2*)b->tw[k], st);
+      if (e != hipSuccess) { destroy_batch(b); return hip_fail(e, "filter spectra launch"); }
+    }
+    if (hipMalloc(&b->items_dev, (size_t)n * sizeof(BatchItem)) != hipSuccess) { destroy_batch(b); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "item table allocation"); }
+    if ((e = hipMemcpyAsync(b->items_dev, b->items_host.data(), (size_t)n * sizeof(BatchItem), hipMemcpyHostToDevice, st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "item table upload"); }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "batch plan synchronisation"); }
+    *out = b;
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_batch_plan");
+  }
+}
+
+ols_status_t ols_batched(ols_batch_t b, ols_stream_t stream) {
+  try {
+    if (!b) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL");
+    if (b->total_units == 0) return OLS_SUCCESS;
+    const int64_t grid = b->total_units < b->grid ? b->total_units : b->grid;
+    hipLaunchKernelGGL(ols_batched_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
+                       (const BatchItem*)b->items_dev, b->n, b->total_units, (const float2*)b->tw[0],
+                       (const float2*)b->tw[1], (const float2*)b->tw[2], (const float2*)b->tw[3],
+                       (const float2*)b->tw[4]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_batched");
+  }
+}
+
+ols_status_t ols_batch_get_info(ols_batch_t b, int64_t* total_units, int32_t* grid, int32_t* n) {
+  if (!b) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL");
+  if (total_units) *total_units = b->total_units;
+  if (grid) *grid = (int32_t)(b->total_units < b->grid ? b->total_units : b->grid);
+  if (n) *n = b->n;
+  return OLS_SUCCESS;
+}
+
+ols_status_t ols_batch_get_item(ols_batch_t b, int32_t i, int32_t* N, int32_t* H, int32_t* D) {
+  if (!b || i < 0 || i >= b->n) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL or item out of range");
+  if (N) *N = b->items_host[i].N;
+  if (H) *H = b->items_host[i].H;
+  if (D) *D = b->items_host[i].D;
+  return OLS_SUCCESS;
+}
+
+ols_status_t ols_batch_destroy(ols_batch_t b) {
+  destroy_batch(b);
   return OLS_SUCCESS;
 }
 

@@ -101,3 +101,36 @@ def backward(s: np.ndarray, gy: np.ndarray, h: np.ndarray, N: int, D: int, H: in
         raise RuntimeError(f"emulator returned {rc}")
     ok = bool(np.all(np.isnan(dsbuf[:guard])) and np.all(np.isnan(dsbuf[guard + Ns:])))
     return dsbuf[guard:guard + Ns].copy(), dh, ok
+
+
+def batched(items, grid: int):
+    """items: list of dicts with s (complex64 [N_s]), h (complex64 [K][M]), N,
+    D, H.  Returns the list of outputs y_i [K_i][N_i_s] (NaN-prefilled, so an
+    unwritten output stays NaN)."""
+    L = emu()
+    L.ols_emu_batched.restype = ctypes.c_int
+    n = len(items)
+    keep = []
+    S = (ctypes.c_void_p * n)()
+    Y = (ctypes.c_void_p * n)()
+    Hp = (ctypes.c_void_p * n)()
+    Ns = (ctypes.c_int64 * n)()
+    K = (ctypes.c_int * n)()
+    M = (ctypes.c_int * n)()
+    Nn = (ctypes.c_int * n)()
+    D = (ctypes.c_int * n)()
+    Hh = (ctypes.c_int * n)()
+    outs = []
+    for i, it in enumerate(items):
+        s = np.ascontiguousarray(it["s"], dtype=np.complex64)
+        h = np.ascontiguousarray(it["h"], dtype=np.complex64)
+        y = np.full((h.shape[0], s.shape[0]), np.complex64(complex(np.nan, np.nan)), dtype=np.complex64)
+        keep += [s, h, y]
+        outs.append(y)
+        S[i], Y[i], Hp[i] = s.ctypes.data, y.ctypes.data, h.ctypes.data
+        Ns[i], K[i], M[i] = s.shape[0], h.shape[0], h.shape[1]
+        Nn[i], D[i], Hh[i] = it["N"], it["D"], it["H"]
+    rc = L.ols_emu_batched(n, S, Y, Ns, Hp, K, M, Nn, D, Hh, grid)
+    if rc != 0:
+        raise RuntimeError(f"emulator returned {rc}")
+    return outs

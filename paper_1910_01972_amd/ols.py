@@ -168,6 +168,66 @@ class OLSConv(torch.nn.Module):
         return OLSConvFunction.apply(s, self.h, self.plan)
 
 
+class OLSBatch:
+    """Many signals with their own filter banks in one persistent launch.
+
+    items: sequence of (s [N_s] complex64, h [K][M] complex64[, N]) on the GPU;
+    N = 0 (or omitted) lets the library choose, a callable fft_length(M, K)
+    (e.g. the tuner's) may choose instead.  Outputs y_i [K_i][N_s_i] are
+    allocated here (or passed as `outputs`) and rewritten by every run().
+    """
+
+    def __init__(self, items, outputs=None, fft_length=None, stream=None):
+        from ._lib import BatchItem
+        n = len(items)
+        if n < 1:
+            raise ValueError("empty batch")
+        arr = (BatchItem * n)()
+        self.inputs, self.outputs = [], []
+        for i, it in enumerate(items):
+            s, h = it[0], it[1]
+            N = int(it[2]) if len(it) > 2 else 0
+            _check_c64(s, "s", 1)
+            _check_c64(h, "h", 2)
+            K, M = int(h.shape[0]), int(h.shape[1])
+            if N == 0 and fft_length is not None:
+                N = int(fft_length(M, K))
+            y = outputs[i] if outputs is not None else torch.empty((K, s.shape[0]), dtype=torch.complex64,
+                                                                   device=s.device)
+            _check_c64(y, "y", 2)
+            self.inputs.append((s, h))
+            self.outputs.append(y)
+            arr[i] = BatchItem(s.data_ptr(), int(s.shape[0]), h.data_ptr(), K, M, N, y.data_ptr())
+        self._handle = ctypes.c_void_p()
+        check(lib().ols_batch_plan(ctypes.byref(self._handle), arr, n, _stream_handle(stream)), "ols_batch_plan")
+        self.n = n
+
+    def info(self) -> dict:
+        u, g, n = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().ols_batch_get_info(self._handle, ctypes.byref(u), ctypes.byref(g), ctypes.byref(n)),
+              "ols_batch_get_info")
+        return {"units": u.value, "grid": g.value, "n": n.value}
+
+    def item(self, i: int) -> dict:
+        v = [ctypes.c_int32() for _ in range(3)]
+        check(lib().ols_batch_get_item(self._handle, int(i), *[ctypes.byref(x) for x in v]), "ols_batch_get_item")
+        return dict(zip(("N", "H", "D"), (x.value for x in v)))
+
+    def run(self, stream=None):
+        """One persistent launch over every item; returns the outputs."""
+        check(lib().ols_batched(self._handle, _stream_handle(stream)), "ols_batched")
+        return self.outputs
+
+    def close(self) -> None:
+        h = getattr(self, "_handle", None)
+        if h is not None and h.value:
+            lib().ols_batch_destroy(h)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+
 def ols_conv(s: torch.Tensor, h: torch.Tensor, N: int = 0, stream=None) -> torch.Tensor:
     """One-shot overlap-and-save convolution: y[K][N_s]."""
     plan = OLSPlan(h, N=N, stream=stream)

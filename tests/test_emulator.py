@@ -137,3 +137,21 @@ def test_adjoint_vs_oracle(Ns, K, M, N, grid):
     rh = adjoint.grad_filters(g, s, M)
     assert np.linalg.norm(ds - rs) <= 1e-5 * np.linalg.norm(rs)
     assert np.all(np.linalg.norm(dh - rh, axis=1) <= 1e-5 * np.linalg.norm(rh, axis=1))
+
+
+def test_batched_walk_vs_oracle():
+    """The batched kernel's unit table and cross-item walk, for several grids."""
+    specs = [(5000, 3, 40, 256), (0, 2, 10, 512), (20000, 1, 100, 1024), (9000, 4, 513, 2048),
+             (30000, 2, 300, 4096), (1, 1, 1, 256), (7777, 5, 64, 512)]
+    items = []
+    for i, (Ns, K, M, N) in enumerate(specs):
+        s, h = workloads.make_signal_filters(Ns, K, M, seed=i + 1)
+        D = default_delay(N, M)
+        items.append(dict(s=s, h=h, N=N, D=D, H=N - D))
+    for grid in (1, 3, 17, 400):
+        outs = emu.batched(items, grid)
+        for it, y in zip(items, outs):
+            if it["s"].shape[0] == 0:
+                continue
+            assert not np.isnan(y).any()
+            assert np.all(_rel(y, conv.direct_conv(it["s"], it["h"])) <= 1e-5)
