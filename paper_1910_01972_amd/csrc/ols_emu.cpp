@@ -144,14 +144,15 @@ std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<flo
 }
 
 // Units [u0, u1) of one signal through the kernel's per-lane code (the body
-// of the device range function).
+// of the device range function); a unit is one tile and NF filters.
 template <int N>
 void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int K, int D, int H, int64_t u0,
-                   int64_t u1, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw) {
+                   int64_t u1, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw, int NF = 1) {
   using GE = Geo<N>;
+  const int KG = (K + NF - 1) / NF;
   std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
-  int64_t tile = u0 / K;
-  int r = (int)(u0 - tile * K);
+  int64_t tile = u0 / KG;
+  int rg = (int)(u0 - tile * KG);
   auto forward_tile = [&]() {
     for (int t = 0; t < GE::WG; ++t) {
       const int grp = t / GE::G, g = t % GE::G;
@@ -163,26 +164,30 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
   };
   forward_tile();
   for (int64_t u = u0; u < u1; ++u) {
-    if (r == K) {
-      r = 0;
+    if (rg == KG) {
+      rg = 0;
       ++tile;
       forward_tile();
     }
-    for (int t = 0; t < GE::WG; ++t) {
-      const int g = t % GE::G;
-      float2 a[16];
-      for (int i = 0; i < 16; ++i) a[i] = A[t][i];
-      load_spectrum<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), F, r, g);
-      product_pass<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), a);
+    for (int f = 0; f < NF; ++f) {
+      const int r = rg * NF + f;
+      if (r >= K) continue;  // padded last group: computed on the device, never stored
+      for (int t = 0; t < GE::WG; ++t) {
+        const int g = t % GE::G;
+        float2 a[16];
+        for (int i = 0; i < 16; ++i) a[i] = A[t][i];
+        load_spectrum<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), F, r, g);
+        product_pass<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), a);
+      }
+      exchange_phase<N, GE::P - 2, GE::P - 1, GE::P - 2>(xs, G);
+      inv_from<N, GE::P - 2>(xs, G, tw);
+      for (int t = 0; t < GE::WG; ++t) {
+        const int grp = t / GE::G, g = t % GE::G;
+        const int64_t seg = tile * GE::SEGS + grp;
+        store_valid<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
+      }
     }
-    exchange_phase<N, GE::P - 2, GE::P - 1, GE::P - 2>(xs, G);
-    inv_from<N, GE::P - 2>(xs, G, tw);
-    for (int t = 0; t < GE::WG; ++t) {
-      const int grp = t / GE::G, g = t % GE::G;
-      const int64_t seg = tile * GE::SEGS + grp;
-      store_valid<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
-    }
-    ++r;
+    ++rg;
   }
 }
 
@@ -194,15 +199,16 @@ int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, i
   const std::vector<float2> F = spectra<N>(h, K, M, table, &guards);
   if (!guards) return 2;
   auto tw = lane_twiddles<N>(table);
+  const int nf = choose_nf(N, K);
   const int64_t nseg = (Ns + H - 1) / H;
   const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
-  const int64_t U = ntiles * K;
+  const int64_t U = ntiles * ((K + nf - 1) / nf);
   if (grid > U) grid = (int)U;
   Group<N> G;
   G.poison();
   for (int b = 0; b < grid; ++b) {
     const int64_t u0 = first_unit(U, grid, b), u1 = first_unit(U, grid, b + 1);
-    if (u0 < u1) forward_range<N>(s, Ns, F.data(), y, K, D, H, u0, u1, G, tw);
+    if (u0 < u1) forward_range<N>(s, Ns, F.data(), y, K, D, H, u0, u1, G, tw, nf);
   }
   return G.guards_ok() ? 0 : 3;
 }
@@ -329,7 +335,7 @@ struct EmuItem {
   float2* y;
   std::vector<float2> F;
   int64_t Ns, unit_begin, units;
-  int K, M, N, D, H;
+  int K, M, N, D, H, nf;
 };
 
 template <int N>
@@ -339,7 +345,7 @@ struct RangeN {
     static thread_local Group<N>* G = nullptr;
     if (!G) { G = new Group<N>(); G->poison(); }
     auto tw = lane_twiddles<N>(build_twiddles<N>());
-    forward_range<N>(it.s, it.Ns, it.F.data(), it.y, it.K, it.D, it.H, a, b, *G, tw);
+    forward_range<N>(it.s, it.Ns, it.F.data(), it.y, it.K, it.D, it.H, a, b, *G, tw, it.nf);
     return G->guards_ok() ? 0 : 3;
   }
 };
@@ -507,10 +513,11 @@ int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t
     it.N = N[i];
     it.D = D[i];
     it.H = H[i];
+    it.nf = ols::choose_nf_batched(it.N, it.K);
     const int segs = 4096 / it.N;
     const int64_t nseg = (it.Ns + it.H - 1) / it.H;
     it.unit_begin = units;
-    it.units = ((nseg + segs - 1) / segs) * it.K;
+    it.units = ((nseg + segs - 1) / segs) * ((it.K + it.nf - 1) / it.nf);
     units += it.units;
     if (dispatch<SpecN>(it.N, &it, (const float2*)h[i]) != 0) return 2;
   }

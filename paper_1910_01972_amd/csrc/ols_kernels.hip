@@ -233,16 +233,32 @@ struct BatchItem {
   int64_t Ns;
   int64_t unit_begin;
   int64_t units;
-  int32_t K, M, N, D, H, pad;
+  int32_t K, M, N, D, H, nf;
 };
 
-// One filter per unit in the batched kernel: with every N in one kernel the
-// register allocation is the maximum over all branches, and the two-filter
-// body would push it past two waves per SIMD.
-template <int N>
+// Each (N, filters per unit) body is its own non-inlined function, so its
+// registers are allocated on their own and the kernel needs only the
+// maximum, not the sum, over the branches it may take.
+template <int N, int NF>
 __device__ __attribute__((noinline)) void batched_item_range(const BatchItem& it, const float2* twt, int64_t a,
                                                              int64_t b, float2* lds, int& par) {
-  forward_range<N, 1>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, twt, a, b, lds, par);
+  forward_range<N, NF>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, twt, a, b, lds, par);
+}
+
+// Two filters per unit only up to N = 2048 here (BATCH_NF2_MAX_N): the
+// N = 4096 two-filter body needs more than 256 registers as a separate
+// function, which would drop the whole kernel to one wave per SIMD.
+
+template <int N>
+__device__ __forceinline__ void batched_item(const BatchItem& it, const float2* twt, int64_t a, int64_t b,
+                                             float2* lds, int& par) {
+  if constexpr (N <= BATCH_NF2_MAX_N) {
+    if (it.nf == 2) {
+      batched_item_range<N, 2>(it, twt, a, b, lds, par);
+      return;
+    }
+  }
+  batched_item_range<N, 1>(it, twt, a, b, lds, par);
 }
 
 __global__ __launch_bounds__(256) void ols_batched_kernel(const BatchItem* __restrict__ items, int nitems,
@@ -270,11 +286,11 @@ __global__ __launch_bounds__(256) void ols_batched_kernel(const BatchItem* __res
     if (end <= u) continue;  // items without units
     const int64_t a = u - it.unit_begin, b = (u1 < end ? u1 : end) - it.unit_begin;
     switch (it.N) {
-      case 256: batched_item_range<256>(it, tw256, a, b, lds, par); break;
-      case 512: batched_item_range<512>(it, tw512, a, b, lds, par); break;
-      case 1024: batched_item_range<1024>(it, tw1024, a, b, lds, par); break;
-      case 2048: batched_item_range<2048>(it, tw2048, a, b, lds, par); break;
-      default: batched_item_range<4096>(it, tw4096, a, b, lds, par); break;
+      case 256: batched_item<256>(it, tw256, a, b, lds, par); break;
+      case 512: batched_item<512>(it, tw512, a, b, lds, par); break;
+      case 1024: batched_item<1024>(it, tw1024, a, b, lds, par); break;
+      case 2048: batched_item<2048>(it, tw2048, a, b, lds, par); break;
+      default: batched_item<4096>(it, tw4096, a, b, lds, par); break;
     }
     u = it.unit_begin + b;
   }
@@ -491,9 +507,6 @@ double cost_per_output(int N, int M, int K) {
   return work / ((double)K * H);
 }
 
-// Filters per work unit: two interleaved transforms when registers allow it
-// (N <= 4096) and the filter count wastes little on a padded last group.
-int choose_nf(int N, int K) { return (N <= 4096 && (K % 2 == 0 || K >= 9)) ? 2 : 1; }
 
 template <int N>
 struct Kern {
@@ -911,12 +924,12 @@ ols_status_t ols_batch_plan(ols_batch_t* out, const ols_batch_item_t* items, int
       d.N = N;
       d.D = default_delay(N, it.M);
       d.H = N - d.D;
-      d.pad = 0;
+      d.nf = choose_nf_batched(N, it.K);
       const int segs = 4096 / N;  // transforms per 256-thread workgroup
       const int64_t nseg = (it.N_s + d.H - 1) / d.H;
       const int64_t ntiles = (nseg + segs - 1) / segs;
       d.unit_begin = units;
-      d.units = ntiles * it.K;
+      d.units = ntiles * ((it.K + d.nf - 1) / d.nf);
       units += d.units;
       spec_elems += (size_t)it.K * N;
     }

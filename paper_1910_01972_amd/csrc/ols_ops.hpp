@@ -129,6 +129,13 @@ OLS_HD void zero_lags(float2* __restrict__ part, int M, int g) {
   }
 }
 
+// Filters per work unit of the forward kernels: two interleaved transforms when
+// registers allow it (N <= 4096) and the filter count wastes little on a
+// padded last group; the batched kernel allows two only up to N = 2048.
+constexpr int BATCH_NF2_MAX_N = 2048;
+OLS_HD int choose_nf(int N, int K) { return (N <= 4096 && (K % 2 == 0 || K >= 9)) ? 2 : 1; }
+OLS_HD int choose_nf_batched(int N, int K) { return N <= BATCH_NF2_MAX_N ? choose_nf(N, K) : 1; }
+
 // Partition arithmetic shared by the persistent kernels: workgroup b of P
 // owns units [first_unit(b), first_unit(b+1)); owner(u) inverts it.
 OLS_HD int64_t first_unit(int64_t U, int64_t P, int64_t b) { return U * b / P; }

@@ -69,6 +69,8 @@ CASES = [
     (9000, 4, 513, 2048, None, 1),    # one workgroup does everything
     (12345, 2, 2048, 4096, 1, 3),     # tiny hop
     (30000, 2, 3000, 8192, None, 4),  # long filter, N = 8192
+    (20000, 9, 100, 1024, None, 7),   # odd K >= 9: two filters per unit, padded last group
+    (15000, 6, 300, 2048, None, 5),   # even K: two filters per unit
 ]
 
 
