@@ -186,8 +186,8 @@ def batched_measurement(steps: int, warmup: int) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -286,8 +286,8 @@ def main():
     plan.close()
     del y
     torch.cuda.empty_cache()
-    rec["fwd_bwd"] = fwd_bwd_measurement(args.steps, args.warmup)
-    rec["batched"] = batched_measurement(max(3, args.steps // 5), 2)
+    rec["fwd_bwd"] = fwd_bwd_measurement(min(args.steps, 100), min(args.warmup, 50))
+    rec["batched"] = batched_measurement(max(3, min(args.steps, 200) // 20), 3)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(s_np, h_np, args.cpu_sample)
     print(json.dumps(rec), flush=True)
