@@ -26,6 +26,8 @@ the Overlap-and-Save Method in Shared Memory"):
   filter spectrum, inverse FFT, discard of the M-1 aliased samples.
 * ``adjoint``              -- the adjoint (gradient) of eq. (1) with respect to
   the signal and to the filters, by direct correlation.
+* ``post``                 -- post-processing of the output (sec. 4): the
+  power |y|^2 and the numerical derivative (backward difference).
 
 Every function is pinned by tests in ``tests/test_oracle*.py`` against things
 other than itself: hand-derived fixtures under ``tests/golden/``, closed forms
@@ -34,4 +36,4 @@ inputs, numpy's own FFT/convolve as library cross-checks, and the invariance of
 the OLS result under the segment length (sec. 3.2).
 """
 
-from . import conv, adjoint  # noqa: F401
+from . import conv, adjoint, post  # noqa: F401

@@ -282,3 +282,53 @@ def pin_adjoint_finite_differences(conv, grad_signal, grad_filters):
             fd = (loss(s, h + e) - loss(s, h - e)) / (2 * eps)
             want = dh[r, k].real if part == "re" else dh[r, k].imag
             assert abs(fd - want) < 1e-10, f"dh[{r},{k}].{part}: fd {fd} vs {want}"
+
+
+# ---------------------------------------------------------- post-processing
+
+def pin_post_golden(power, derivative, conv):
+    d = load_golden("post_small.json")
+    s = _c(d, "s_re", "s_im")
+    h = _c(d, "h_re", "h_im")
+    y = conv(s, h)
+    _close(y, _c(d, "y_re", "y_im"), 1e-14, "post_small y")
+    _close(derivative(y), _c(d, "d_re", "d_im"), 1e-14, "post_small derivative")
+    _close(power(y), np.asarray(d["p"], dtype=np.float64), 1e-14, "post_small power")
+
+
+def pin_power_closed_forms(power):
+    rng = np.random.default_rng(31)
+    w = rng.uniform(-np.pi, np.pi, 64)
+    _close(power(np.exp(1j * w)), np.ones(64), 1e-14, "unit circle")
+    r = rng.uniform(-3, 3, 64)
+    _close(power(r + 0j), r * r, 1e-14, "real axis")
+    _close(power(1j * r), r * r, 1e-14, "imaginary axis")
+    z = rand_c(rng, 3, 50)
+    assert np.asarray(power(z)).dtype.kind == "f" and np.all(power(z) >= 0)
+    # Parseval: the summed power equals the summed power of the spectrum / N
+    _close(np.sum(power(z), axis=-1), np.sum(power(np.fft.fft(z)), axis=-1) / 50, 1e-12, "Parseval")
+
+
+def pin_derivative_closed_forms(derivative, conv):
+    rng = np.random.default_rng(32)
+    # boxcar on a constant: y[n] = min(n+1, M), so d[n] = 1 for n < M, else 0
+    M, Ns = 9, 40
+    d = derivative(conv(np.ones(Ns), np.ones((1, M))))
+    _close(d, (np.arange(Ns) < M).astype(float)[None, :], 1e-13, "boxcar step")
+    # telescoping: the running sum of the difference gives back y
+    y = rand_c(rng, 2, 77)
+    _close(np.cumsum(derivative(y), axis=-1), y, 1e-13, "telescoping")
+    # complex exponential: once the filter is full, d[n] = y[n] (1 - e^{-iw})
+    w = 0.37
+    n = np.arange(200)
+    h = rand_c(rng, 1, 16)
+    y = conv(np.exp(1j * w * n), h)
+    d = derivative(y)
+    _close(d[:, 16:], y[:, 16:] * (1 - np.exp(-1j * w)), 1e-12, "exponential")
+    # a delta at m: y = h shifted, d is h[k] - h[k-1] shifted
+    s = np.zeros(30, dtype=complex)
+    s[5] = 1
+    h = rand_c(rng, 1, 6)
+    want = np.zeros((1, 30), dtype=complex)
+    want[0, 5:12] = np.concatenate([h[0], [0]]) - np.concatenate([[0], h[0]])
+    _close(derivative(conv(s, h)), want, 1e-13, "delta")

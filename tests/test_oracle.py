@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from oracle import adjoint, conv
+from oracle import adjoint, conv, post
 import oracle_pins as P
 import workloads
 
@@ -208,3 +208,24 @@ def test_grad_signal_at():
     P._close(adjoint.grad_signal_at(g, h, idx), adjoint.grad_signal(g, h)[idx], 1e-12, "grad_signal_at")
     with pytest.raises(IndexError):
         adjoint.grad_signal_at(g, h, [500])
+
+
+def test_post_golden():
+    P.pin_post_golden(post.power, post.derivative, conv.direct_conv)
+    P.pin_post_golden(post.power, post.derivative, conv.direct_conv_loops)
+
+
+def test_post_closed_forms():
+    P.pin_power_closed_forms(post.power)
+    P.pin_derivative_closed_forms(post.derivative, conv.direct_conv)
+
+
+def test_post_composed_and_sampled():
+    rng = np.random.default_rng(33)
+    s = P.rand_c(rng, 3000)
+    h = P.rand_c(rng, 3, 40)
+    y = conv.direct_conv(s, h)
+    P._close(post.conv_power(s, h), post.power(y), 1e-14, "conv_power")
+    P._close(post.conv_derivative(s, h), post.derivative(y), 1e-14, "conv_derivative")
+    idx = np.array([0, 1, 2, 39, 40, 41, 1234, 2999])
+    P._close(post.derivative_at(s, h, idx), post.derivative(y)[:, idx], 1e-12, "derivative_at")

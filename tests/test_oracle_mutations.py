@@ -168,3 +168,55 @@ def _dh_shift(g, s, M):
 def test_adjoint_mutants_caught(ds, dh):
     _expect_caught(lambda: P.pin_adjoint_dot_product(conv.direct_conv, ds, dh),
                    lambda: P.pin_adjoint_finite_differences(conv.direct_conv, ds, dh))
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except AssertionError:
+        return True
+    return False
+
+
+def _deriv_forward(y):
+    y = np.asarray(y, dtype=np.complex128)
+    d = np.zeros_like(y)
+    d[..., :-1] = y[..., 1:] - y[..., :-1]
+    return d
+
+
+def _deriv_sign(y):
+    y = np.asarray(y, dtype=np.complex128)
+    d = y.copy()
+    d[..., 1:] += y[..., :-1]
+    return d
+
+
+def _deriv_wrap(y):
+    y = np.asarray(y, dtype=np.complex128)
+    return y - np.roll(y, 1, axis=-1)
+
+
+def _deriv_no_first(y):
+    y = np.asarray(y, dtype=np.complex128)
+    d = np.zeros_like(y)
+    d[..., 1:] = y[..., 1:] - y[..., :-1]
+    return d
+
+
+@pytest.mark.parametrize("mutant", [_deriv_forward, _deriv_sign, _deriv_wrap, _deriv_no_first])
+def test_derivative_mutants_fail(mutant):
+    from oracle import post
+    assert (_fails(P.pin_post_golden, post.power, mutant, conv.direct_conv)
+            or _fails(P.pin_derivative_closed_forms, mutant, conv.direct_conv))
+
+
+@pytest.mark.parametrize("mutant", [
+    lambda y: np.asarray(y).real ** 2,
+    lambda y: np.abs(np.asarray(y)),
+    lambda y: (np.asarray(y) ** 2).real,
+])
+def test_power_mutants_fail(mutant):
+    from oracle import post
+    assert (_fails(P.pin_post_golden, mutant, post.derivative, conv.direct_conv)
+            or _fails(P.pin_power_closed_forms, mutant))
