@@ -16,6 +16,8 @@ the Overlap-and-Save Method in Shared Memory"):
 * ``conv.direct_conv``     -- eq. (1), discrete linear convolution, zero history.
 * ``conv.direct_conv_at``  -- eq. (1) evaluated at chosen output indices only.
 * ``conv.direct_conv_loops`` -- eq. (1) as explicit Python loops (tiny inputs).
+* ``conv.direct_conv_real`` / ``direct_conv_real_at`` -- eq. (1) for a real
+  signal and real filters (R2R), float64.
 * ``conv.fft`` / ``conv.ifft`` -- hand-written iterative radix-2 Cooley-Tukey
   FFT with explicit bit reversal (the FFT named in the introduction and sec. 3.4).
 * ``conv.dft``             -- the O(N^2) DFT definition (tiny inputs).

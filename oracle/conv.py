@@ -31,6 +31,8 @@ __all__ = [
     "direct_conv",
     "direct_conv_at",
     "direct_conv_loops",
+    "direct_conv_real",
+    "direct_conv_real_at",
     "dft",
     "fft",
     "ifft",
@@ -100,6 +102,44 @@ def direct_conv(s, h, chunk: int = 1 << 16) -> np.ndarray:
         n1 = min(Ns, n0 + chunk)
         y[:, n0:n1] = (windows[n0:n1] @ hrev).T
     return y
+
+
+def direct_conv_real(s, h, chunk: int = 1 << 16) -> np.ndarray:
+    """eq. (1) for a real signal and real filters (the R2R case of sec. 1 and
+    3.4), in float64: the same sum as ``direct_conv`` with real operands.
+    Returns float64 of shape (K, N_s)."""
+    s = np.asarray(s, dtype=np.float64)
+    h = np.asarray(h, dtype=np.float64)
+    if h.ndim == 1:
+        h = h[None, :]
+    if s.ndim != 1 or h.ndim != 2 or h.shape[1] < 1:
+        raise ValueError("signal must be 1-D and filters (K, M) with M >= 1")
+    K, M = h.shape
+    Ns = s.shape[0]
+    y = np.empty((K, Ns), dtype=np.float64)
+    if Ns == 0:
+        return y
+    padded = np.concatenate([np.zeros(M - 1), s])
+    windows = np.lib.stride_tricks.sliding_window_view(padded, M)  # (Ns, M)
+    hrev = np.ascontiguousarray(h[:, ::-1].T)
+    for n0 in range(0, Ns, chunk):
+        n1 = min(Ns, n0 + chunk)
+        y[:, n0:n1] = (windows[n0:n1] @ hrev).T
+    return y
+
+
+def direct_conv_real_at(s, h, idx) -> np.ndarray:
+    """``direct_conv_real`` at the output indices idx only (eq. 1 is local)."""
+    s = np.asarray(s, dtype=np.float64)
+    h = np.atleast_2d(np.asarray(h, dtype=np.float64))
+    idx = np.asarray(idx, dtype=np.int64).ravel()
+    K, M = h.shape
+    Ns = s.shape[0]
+    if np.any(idx < 0) or np.any(idx >= Ns):
+        raise IndexError("output index out of range")
+    src = idx[:, None] - np.arange(M, dtype=np.int64)[None, :]
+    vals = np.where(src >= 0, s[np.clip(src, 0, max(Ns - 1, 0))], 0.0)
+    return (vals @ h.T).T
 
 
 def direct_conv_at(s, h, idx) -> np.ndarray:

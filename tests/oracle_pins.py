@@ -332,3 +332,33 @@ def pin_derivative_closed_forms(derivative, conv):
     want = np.zeros((1, 30), dtype=complex)
     want[0, 5:12] = np.concatenate([h[0], [0]]) - np.concatenate([[0], h[0]])
     _close(derivative(conv(s, h)), want, 1e-13, "delta")
+
+
+# ------------------------------------------------------------------ R2R
+
+def pin_real_conv(conv_real):
+    """Real-data convolution (R2R): hand-worked fixture, library cross-check,
+    brute force, closed forms."""
+    d = load_golden("ols_boxcar_n4.json")
+    _close(conv_real(np.asarray(d["s_re"], float), np.asarray(d["h_re"], float)),
+           np.asarray(d["y_re"], float), 1e-14, "boxcar fixture")
+    rng = np.random.default_rng(41)
+    s = rng.standard_normal(300)
+    h = rng.standard_normal((3, 17))
+    y = conv_real(s, h)
+    assert y.dtype == np.float64 and y.shape == (3, 300)
+    for r in range(3):
+        _close(y[r], np.convolve(s, h[r])[:300], 1e-12, "np.convolve")
+    # brute force on a tiny case
+    s = rng.standard_normal(9)
+    h = rng.standard_normal((2, 4))
+    want = np.zeros((2, 9))
+    for r in range(2):
+        for n in range(9):
+            want[r, n] = sum(h[r, k] * s[n - k] for k in range(4) if n - k >= 0)
+    _close(conv_real(s, h), want, 1e-14, "brute force")
+    # delta filter is the identity; a shifted delta delays by the shift
+    s = rng.standard_normal(50)
+    e = np.zeros((1, 6))
+    e[0, 5] = 1
+    _close(conv_real(s, e)[0], np.concatenate([np.zeros(5), s[:45]]), 1e-15, "shifted delta")

@@ -229,3 +229,19 @@ def test_post_composed_and_sampled():
     P._close(post.conv_derivative(s, h), post.derivative(y), 1e-14, "conv_derivative")
     idx = np.array([0, 1, 2, 39, 40, 41, 1234, 2999])
     P._close(post.derivative_at(s, h, idx), post.derivative(y)[:, idx], 1e-12, "derivative_at")
+
+
+def test_real_conv_pins():
+    P.pin_real_conv(conv.direct_conv_real)
+
+
+def test_real_conv_at_and_complex_agreement():
+    rng = np.random.default_rng(42)
+    s = rng.standard_normal(5000)
+    h = rng.standard_normal((4, 300))
+    y = conv.direct_conv_real(s, h)
+    idx = np.array([0, 1, 298, 299, 300, 4999, 2500])
+    P._close(conv.direct_conv_real_at(s, h, idx), y[:, idx], 1e-12, "real_at")
+    yc = conv.direct_conv(s.astype(complex), h.astype(complex))
+    P._close(yc.real, y, 1e-12, "complex path real part")
+    assert np.abs(yc.imag).max() == 0.0

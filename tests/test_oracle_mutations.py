@@ -220,3 +220,26 @@ def test_power_mutants_fail(mutant):
     from oracle import post
     assert (_fails(P.pin_post_golden, mutant, post.derivative, conv.direct_conv)
             or _fails(P.pin_power_closed_forms, mutant))
+
+
+def _real_corr(s, h):
+    # correlation instead of convolution (filter not reversed)
+    s = np.asarray(s, float)
+    h = np.atleast_2d(np.asarray(h, float))
+    K, M = h.shape
+    padded = np.concatenate([np.zeros(M - 1), s])
+    win = np.lib.stride_tricks.sliding_window_view(padded, M)
+    return (win @ h.T).T
+
+
+def _real_no_history(s, h):
+    s = np.asarray(s, float)
+    h = np.atleast_2d(np.asarray(h, float))
+    y = conv.direct_conv_real(s, h)
+    y[:, : h.shape[1] - 1] = 0
+    return y
+
+
+@pytest.mark.parametrize("mutant", [_real_corr, _real_no_history])
+def test_real_conv_mutants_fail(mutant):
+    assert _fails(P.pin_real_conv, mutant)

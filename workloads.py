@@ -45,6 +45,8 @@ WORKLOADS = {
     "filter_bank_2p23_k32_m256": Workload("filter_bank_2p23_k32_m256", 1 << 23, 32, 256, 2048, 2),
     # differentiable: 2^22 samples, 16 filters of 512 taps, N = 4096
     "grad_2p22_k16_m512": Workload("grad_2p22_k16_m512", 1 << 22, 16, 512, 4096, 5),
+    # real data (R2R): 2^23 real samples, 32 real filters of 256 taps, N = 2048
+    "filter_bank_real_2p23_k32_m256": Workload("filter_bank_real_2p23_k32_m256", 1 << 23, 32, 256, 2048, 6),
 }
 
 
@@ -62,6 +64,15 @@ def make_signal_filters(Ns: int, K: int, M: int, seed: int, rng: np.random.Gener
     hr = g.standard_normal((K, M)) * scale
     hi = g.standard_normal((K, M)) * scale
     h = (hr + 1j * hi).astype(np.complex64)
+    return s, h
+
+
+def make_real_signal_filters(Ns: int, K: int, M: int, seed: int):
+    """Real-data case (R2R): (s float32 [Ns] ~ U[-1, 1], h float32 [K, M] ~
+    N(0, 1/M)), drawn in that order from the seed's stream."""
+    g = _rng(seed)
+    s = g.uniform(-1.0, 1.0, Ns).astype(np.float32)
+    h = (g.standard_normal((K, M)) / np.sqrt(M)).astype(np.float32)
     return s, h
 
 
