@@ -122,6 +122,60 @@ def fwd_bwd_measurement(steps: int, warmup: int) -> dict:
     }
 
 
+def variants_measurement(steps: int, warmup: int) -> dict:
+    """The fused post-processing options (power, derivative) on the benchmark
+    filter bank, and the real-to-real path on the same shape with real data,
+    each timed with HIP events on the launch stream; bytes are the algorithmic
+    HBM bytes of each variant (signal + outputs + taps)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1910_01972_amd.ols import OLSPlan
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    out = {}
+    wl = workloads.WORKLOADS["filter_bank_2p23_k32_m256"]
+    s_np, h_np = workloads.make_signal_filters(wl.Ns, wl.K, wl.M, seed=wl.seed)
+    s, h = torch.from_numpy(s_np).cuda(), torch.from_numpy(h_np).cuda()
+    for name, kw, ybytes in (("power", {"power": True}, 4), ("derivative", {"derivative": True}, 8)):
+        plan = OLSPlan(h, N=wl.N, **kw)
+        y = torch.empty((wl.K, wl.Ns), dtype=torch.float32 if ybytes == 4 else torch.complex64, device="cuda")
+        ms = timed(lambda: plan.forward(s, y))
+        alg = ybytes * wl.K * wl.Ns + 8 * wl.Ns + 8 * wl.K * wl.M
+        out[name] = {"workload": wl.name, "ms": ms, "samples_per_s": wl.K * wl.Ns / (ms * 1e-3),
+                     "alg_GBps": alg / (ms * 1e-3) / 1e9}
+        plan.close()
+        del y
+    del s, h
+    wr = workloads.WORKLOADS["filter_bank_real_2p23_k32_m256"]
+    s_np, h_np = workloads.make_real_signal_filters(wr.Ns, wr.K, wr.M, seed=wr.seed)
+    s, h = torch.from_numpy(s_np).cuda(), torch.from_numpy(h_np).cuda()
+    plan = OLSPlan(h, N=wr.N)
+    y = torch.empty((wr.K, wr.Ns), dtype=torch.float32, device="cuda")
+    ms = timed(lambda: plan.forward(s, y))
+    alg = 4 * wr.K * wr.Ns + 4 * wr.Ns + 4 * wr.K * wr.M
+    out["r2r"] = {"workload": wr.name, "ms": ms, "samples_per_s": wr.K * wr.Ns / (ms * 1e-3),
+                  "alg_GBps": alg / (ms * 1e-3) / 1e9}
+    plan.close()
+    del y
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_measurement(steps: int, warmup: int) -> dict:
     """The uneven batch (256 signals, N_s log-uniform in [2^14, 2^22], K ~
     U{1..16}, M log-uniform in [16, 1024]) as ONE persistent launch captured in
@@ -278,7 +332,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "ols_forward_kernel<2048, 2>",
+            "kernel": "ols_forward_kernel<2048, 2, false, false>",
             "kernel_ms": kernel_ms,
             "alg_bytes_per_launch": alg_bytes,
         },
@@ -288,6 +342,7 @@ def main():
     torch.cuda.empty_cache()
     rec["fwd_bwd"] = fwd_bwd_measurement(min(args.steps, 100), min(args.warmup, 50))
     rec["batched"] = batched_measurement(max(3, min(args.steps, 200) // 20), 3)
+    rec["variants"] = variants_measurement(min(args.steps, 100), min(args.warmup, 50))
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(s_np, h_np, args.cpu_sample)
     print(json.dumps(rec), flush=True)

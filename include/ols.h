@@ -75,6 +75,38 @@ typedef enum {
 ols_status_t ols_plan(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int32_t N, ols_stream_t stream);
 
 /*
+ * ols_plan_ex -- ols_plan with flags (any combination):
+ *   OLS_POST_DERIVATIVE  fused post-processing (sec. 4, the non-local example
+ *                        of the paper): y'_r[n] = y_r[n] - y_r[n-1],
+ *                        y_r[-1] = 0.  Being a convolution with [1, -1] it is
+ *                        folded into the filter spectra, which adds one
+ *                        aliased sample per segment: M + 1 <= N is required
+ *                        and the hop is at most N - M.
+ *   OLS_POST_POWER       fused per-element post-processing (sec. 4): the
+ *                        power |y_r[n]|^2 is written instead of y, as float32
+ *                        [K][N_s] (half the output bytes of complex64).
+ *   OLS_REAL             real-to-real convolution (sec. 1 and 3.4, R2R): h is
+ *                        float32 [K][M], and ols_forward takes s as float32
+ *                        [N_s] and writes y as float32 [K][N_s].  Two real
+ *                        segments share one complex FFT of length N (one in
+ *                        the real, one in the imaginary part; with real
+ *                        filters the two results come back separated), so a
+ *                        real segment costs half a complex one in arithmetic
+ *                        and in bytes.
+ * Post-processing applies after the derivative (POWER|DERIVATIVE is the power
+ * of the derivative).  Plans with flags do not support ols_backward
+ * (UNSUPPORTED).  Pointers need the alignment of their element type (4 bytes
+ * for float32, 8 for complex64).  Other errors as ols_plan; an unknown flag is
+ * INVALID_VALUE.
+ */
+#define OLS_POST_NONE 0
+#define OLS_POST_DERIVATIVE 1
+#define OLS_POST_POWER 2
+#define OLS_REAL 4
+ols_status_t ols_plan_ex(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int32_t N, int32_t flags,
+                         ols_stream_t stream);
+
+/*
  * ols_plan_update_filters -- replace the K filters of a plan (same K and M),
  * recomputing their spectra on `stream` (stream ordered; forward calls queued
  * later on the same stream see the new filters).  Paper: Alg. 2, forward FFT
@@ -113,10 +145,11 @@ ols_status_t ols_plan_get_spectra(ols_plan_t plan, void* out, ols_stream_t strea
  * computed by overlap-and-save (sec. 3.2) in one fused kernel (sec. 3.4,
  * Alg. 2).
  *
- *   s    device, complex64 [N_s]
+ *   s    device, complex64 [N_s] (float32 [N_s] for an OLS_REAL plan)
  *   N_s  signal length, >= 0 (0 is a successful no-op)
- *   y    device, complex64 [K][N_s] row-major, written completely; must not
- *        overlap s (out of place only)
+ *   y    device, complex64 [K][N_s] row-major (float32 [K][N_s] for a plan
+ *        with OLS_POST_POWER or OLS_REAL), written completely, post-processed
+ *        as the plan's flags say; must not overlap s (out of place only)
  * Errors: INVALID_VALUE (null plan/s/y, N_s < 0, misaligned, overlap,
  * K*N_s*8 overflow), HIP (launch failure).  Allocates nothing.
  */

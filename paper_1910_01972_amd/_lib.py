@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libols.so")
 EMU_PATH = os.path.join(_PKG, "lib", "libols_emu.so")
 
 OLS_SUCCESS = 0
+POST_NONE, POST_DERIVATIVE, POST_POWER = 0, 1, 2
 STATUS_NAMES = {
     0: "OLS_SUCCESS",
     1: "OLS_ERROR_INVALID_VALUE",
@@ -31,6 +32,7 @@ _I64 = ctypes.c_int64
 _PI32 = ctypes.POINTER(ctypes.c_int32)
 SIGNATURES = {
     "ols_plan": (_I32, [ctypes.POINTER(_P), _P, _I32, _I32, _I32, _P]),
+    "ols_plan_ex": (_I32, [ctypes.POINTER(_P), _P, _I32, _I32, _I32, _I32, _P]),
     "ols_plan_update_filters": (_I32, [_P, _P, _P]),
     "ols_plan_set_hop": (_I32, [_P, _I32]),
     "ols_plan_get_info": (_I32, [_P, _PI32, _PI32, _PI32, _PI32, _PI32]),

@@ -117,7 +117,8 @@ std::vector<std::array<float2, Geo<N>::TWR>> lane_twiddles(const std::vector<flo
 
 // Filter spectra in kernel order F[K][16][G] (as the device plan stores them).
 template <int N>
-std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<float2>& table, bool* guards) {
+std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<float2>& table, bool* guards,
+                            bool diff = false, bool real = false) {
   using GE = Geo<N>;
   auto tw = lane_twiddles<N>(table);
   std::vector<float2> F((size_t)K * N);
@@ -130,7 +131,11 @@ std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<flo
       const int grp = t / GE::G, g = t % GE::G;
       const int r = b * GE::SEGS + grp;
       const bool valid = r < K;
-      load_filter<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), h + (int64_t)(valid ? r : 0) * M, M, valid, g);
+      float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
+      const int64_t row = (int64_t)(valid ? r : 0) * M;
+      if (real) load_filter_real<N>(x, reinterpret_cast<const float*>(h) + row, M, valid, diff, g);
+      else if (diff) load_filter_diff<N>(x, h + row, M, valid, g);
+      else load_filter<N>(x, h + row, M, valid, g);
     }
     fwd_from<N, 0>(xs, G, tw);
     for (int t = 0; t < GE::WG; ++t) {
@@ -147,7 +152,8 @@ std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<flo
 // of the device range function); a unit is one tile and NF filters.
 template <int N>
 void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int K, int D, int H, int64_t u0,
-                   int64_t u1, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw, int NF = 1) {
+                   int64_t u1, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw, int NF = 1,
+                   bool power = false, bool real = false) {
   using GE = Geo<N>;
   const int KG = (K + NF - 1) / NF;
   std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
@@ -157,7 +163,9 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
     for (int t = 0; t < GE::WG; ++t) {
       const int grp = t / GE::G, g = t % GE::G;
       const int64_t seg = tile * GE::SEGS + grp;
-      load_segment<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), s, Ns, seg * H - D, g);
+      float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
+      if (real) load_segment_pair<N>(x, reinterpret_cast<const float*>(s), Ns, seg * 2 * H - D, H, g);
+      else load_segment<N>(x, s, Ns, seg * H - D, g);
     }
     fwd_from<N, 0>(xs, G, tw);
     A = xs;
@@ -184,7 +192,12 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
       for (int t = 0; t < GE::WG; ++t) {
         const int grp = t / GE::G, g = t % GE::G;
         const int64_t seg = tile * GE::SEGS + grp;
-        store_valid<N>(*reinterpret_cast<float2(*)[16]>(xs[t].data()), y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
+        const float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
+        float* yr = reinterpret_cast<float*>(y) + (int64_t)r * Ns;
+        if (real && power) store_valid_pair<N, true>(x, yr, Ns, seg * 2 * H, D, H, g);
+        else if (real) store_valid_pair<N, false>(x, yr, Ns, seg * 2 * H, D, H, g);
+        else if (power) store_valid_power<N>(x, yr, Ns, seg * H, D, H, g);
+        else store_valid<N>(x, y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
       }
     }
     ++rg;
@@ -192,23 +205,26 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
 }
 
 template <int N>
-int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y) {
+int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y,
+            int post = 0) {
   using GE = Geo<N>;
   const std::vector<float2> table = build_twiddles<N>();
   bool guards = true;
-  const std::vector<float2> F = spectra<N>(h, K, M, table, &guards);
+  const bool real = (post & 4) != 0;
+  const std::vector<float2> F = spectra<N>(h, K, M, table, &guards, (post & 1) != 0, real);
   if (!guards) return 2;
   auto tw = lane_twiddles<N>(table);
-  const int nf = choose_nf(N, K);
+  const int nf = real ? choose_nf_real(N, K) : choose_nf(N, K);
   const int64_t nseg = (Ns + H - 1) / H;
-  const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
+  const int64_t ntrans = real ? (nseg + 1) / 2 : nseg;
+  const int64_t ntiles = (ntrans + GE::SEGS - 1) / GE::SEGS;
   const int64_t U = ntiles * ((K + nf - 1) / nf);
   if (grid > U) grid = (int)U;
   Group<N> G;
   G.poison();
   for (int b = 0; b < grid; ++b) {
     const int64_t u0 = first_unit(U, grid, b), u1 = first_unit(U, grid, b + 1);
-    if (u0 < u1) forward_range<N>(s, Ns, F.data(), y, K, D, H, u0, u1, G, tw, nf);
+    if (u0 < u1) forward_range<N>(s, Ns, F.data(), y, K, D, H, u0, u1, G, tw, nf, (post & 2) != 0, real);
   }
   return G.guards_ok() ? 0 : 3;
 }
@@ -432,8 +448,9 @@ int dispatch(int N, A... a) {
 
 template <int N>
 struct RunFwd {
-  static int run(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y) {
-    return forward<N>(s, Ns, h, K, M, D, H, grid, y);
+  static int run(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y,
+                 int post) {
+    return forward<N>(s, Ns, h, K, M, D, H, grid, y, post);
   }
 };
 template <int N>
@@ -486,7 +503,17 @@ extern "C" {
 // dataflow.  Returns 0 on success, 2/3 if an LDS guard band was touched, -1 for
 // an unsupported N.
 int ols_emu_forward(int N, const float* s, int64_t Ns, const float* h, int K, int M, int D, int H, int grid, float* y) {
-  return ols::emu::dispatch<ols::emu::RunFwd>(N, (const float2*)s, Ns, (const float2*)h, K, M, D, H, grid, (float2*)y);
+  return ols::emu::dispatch<ols::emu::RunFwd>(N, (const float2*)s, Ns, (const float2*)h, K, M, D, H, grid, (float2*)y,
+                                              0);
+}
+
+// As ols_emu_forward with the flags of ols_plan_ex (1: first difference folded
+// into the spectra, 2: power |y|^2 stored as float [K][Ns], 4: R2R, s float
+// [Ns], h float [K][M], y float [K][Ns]).
+int ols_emu_forward_post(int N, const float* s, int64_t Ns, const float* h, int K, int M, int D, int H, int grid,
+                         int post, float* y) {
+  return ols::emu::dispatch<ols::emu::RunFwd>(N, (const float2*)s, Ns, (const float2*)h, K, M, D, H, grid, (float2*)y,
+                                              post);
 }
 
 // Adjoint through the kernel dataflow: ds[N_s], dh[K][M].

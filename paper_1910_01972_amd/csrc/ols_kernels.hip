@@ -101,12 +101,14 @@ __device__ __forceinline__ void inverse_of_products(float2 (&x)[NF][16], const f
 }
 
 // ---------------------------------------------------------------------------
-// Filter spectra (plan step): F_r = FFT_N(pad(h_r)) / N in kernel order.
+// Filter spectra (plan step): F_r = FFT_N(pad(h_r)) / N in kernel order;
+// h is complex64, or float32 for R2R plans (real != 0).
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const float2* __restrict__ h, int K, int M,
+__global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const void* __restrict__ h, int K, int M,
                                                                         float2* __restrict__ F,
-                                                                        const float2* __restrict__ twt) {
+                                                                        const float2* __restrict__ twt, int diff,
+                                                                        int real) {
   using GE = Geo<N>;
   __shared__ float2 lds[2 * GE::LDS];
   const int tid = threadIdx.x;
@@ -117,7 +119,10 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const fl
   load_lane_twiddles<N>(tw, twt, g);
   float2 x[16];
   const bool valid = r < K;
-  load_filter<N>(x, h + (int64_t)(valid ? r : 0) * M, M, valid, g);
+  const int64_t row = (int64_t)(valid ? r : 0) * M;
+  if (real) load_filter_real<N>(x, (const float*)h + row, M, valid, diff != 0, g);
+  else if (diff) load_filter_diff<N>(x, (const float2*)h + row, M, valid, g);
+  else load_filter<N>(x, (const float2*)h + row, M, valid, g);
   fwd_from<N, 0>(x, lds, par, tw, grp, g);
   if (valid) store_spectrum<N>(x, F, r, g, 1.0f / (float)N);
 }
@@ -143,15 +148,19 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
 // ---------------------------------------------------------------------------
 // Units [u0, u1) of one signal: the body shared by the single-signal kernel
 // and the batched kernel.  `par` carries the LDS buffer parity across calls.
-template <int N, int NF>
-__device__ __forceinline__ void forward_range(const float2* __restrict__ s, int64_t Ns, const float2* __restrict__ F,
-                                              float2* __restrict__ y, int K, int D, int H,
+// REAL (R2R): s and y are float32 and a transform carries a pair of segments
+// (real part 2q, imaginary part 2q+1), so a tile is SEGS pairs.  POWER
+// stores |y|^2 (float32) instead of y.
+template <int N, int NF, bool POWER = false, bool REAL = false>
+__device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
+                                              void* __restrict__ yv, int K, int D, int H,
                                               const float2* __restrict__ twt, int64_t u0, int64_t u1, float2* lds,
                                               int& par) {
   using GE = Geo<N>;
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
   const int KG = (K + NF - 1) / NF;  // filter groups
+  const int64_t step = REAL ? 2 * (int64_t)H : H;  // signal advance per transform
 
   float2 tw[GE::TWR];
   load_lane_twiddles<N>(tw, twt, g);
@@ -160,15 +169,19 @@ __device__ __forceinline__ void forward_range(const float2* __restrict__ s, int6
   int rg = (int)(u0 - tile * KG);
   float2 A[16], x[NF][16];
 
-  // Segment index of this lane's transform; uniform over a wave when a
-  // transform spans whole waves (G >= 64).
+  // Transform index of this lane (a segment, or a segment pair for REAL);
+  // uniform over a wave when a transform spans whole waves (G >= 64).
   auto segment_of = [&](int64_t t) -> int64_t {
     const int64_t sg = t * GE::SEGS + grp;
     return GE::G >= 64 ? wave_uniform64(sg) : sg;
   };
+  auto load = [&](int64_t sg) {
+    if constexpr (REAL) load_segment_pair<N>(x[0], (const float*)sv, Ns, sg * step - D, H, g);
+    else load_segment<N>(x[0], (const float2*)sv, Ns, sg * step - D, g);
+  };
 
   int64_t seg = segment_of(tile);
-  load_segment<N>(x[0], s, Ns, seg * H - D, g);
+  load(seg);
   fwd_from<N, 0>(x[0], lds, par, tw, grp, g);
 #pragma unroll
   for (int i = 0; i < 16; ++i) A[i] = x[0][i];
@@ -178,7 +191,7 @@ __device__ __forceinline__ void forward_range(const float2* __restrict__ s, int6
       rg = 0;
       ++tile;
       seg = segment_of(tile);
-      load_segment<N>(x[0], s, Ns, seg * H - D, g);
+      load(seg);
       fwd_from<N, 0>(x[0], lds, par, tw, grp, g);
 #pragma unroll
       for (int i = 0; i < 16; ++i) A[i] = x[0][i];
@@ -194,15 +207,19 @@ __device__ __forceinline__ void forward_range(const float2* __restrict__ s, int6
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const int r = rg * NF + f;
-      if (NF == 1 || r < K) store_valid<N>(x[f], y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
+      if (NF == 1 || r < K) {
+        if constexpr (REAL) store_valid_pair<N, POWER>(x[f], (float*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
+        else if constexpr (POWER) store_valid_power<N>(x[f], (float*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
+        else store_valid<N>(x[f], (float2*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
+      }
     }
     ++rg;
   }
 }
 
-template <int N, int NF>
-__global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const float2* __restrict__ s, int64_t Ns,
-                                                                 const float2* __restrict__ F, float2* __restrict__ y,
+template <int N, int NF, bool POWER, bool REAL>
+__global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const void* __restrict__ s, int64_t Ns,
+                                                                 const float2* __restrict__ F, void* __restrict__ y,
                                                                  int K, int D, int H, int64_t ntiles,
                                                                  const float2* __restrict__ twt) {
   using GE = Geo<N>;
@@ -213,7 +230,7 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const float2* _
   const int64_t u1 = first_unit(U, gridDim.x, blockIdx.x + 1);
   if (u0 >= u1) return;  // uniform over the workgroup
   int par = 0;
-  forward_range<N, NF>(s, Ns, F, y, K, D, H, twt, u0, u1, lds, par);
+  forward_range<N, NF, POWER, REAL>(s, Ns, F, y, K, D, H, twt, u0, u1, lds, par);
 }
 
 // ---------------------------------------------------------------------------
@@ -242,7 +259,7 @@ struct BatchItem {
 template <int N, int NF>
 __device__ __attribute__((noinline)) void batched_item_range(const BatchItem& it, const float2* twt, int64_t a,
                                                              int64_t b, float2* lds, int& par) {
-  forward_range<N, NF>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, twt, a, b, lds, par);
+  forward_range<N, NF, false>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, twt, a, b, lds, par);
 }
 
 // Two filters per unit only up to N = 2048 here (BATCH_NF2_MAX_N): the
@@ -457,6 +474,7 @@ struct ols_plan_s {
   int block = 0;  // threads per workgroup
   int segs = 0;   // segments per tile
   int nf = 1;     // filters per work unit of the forward kernel
+  int flags = 0;  // OLS_POST_* and OLS_REAL
   int bwd_grid = 0;           // persistent workgroups of the adjoint kernel
   float2* ws_ds = nullptr;    // [bwd_grid][2][SEGS][N] partial ds windows
   float2* part_dh = nullptr;  // [bwd_grid][SEGS][K][M] dh lag partials
@@ -513,9 +531,10 @@ struct Kern {
   using GE = Geo<N>;
   static constexpr bool HAS_NF2 = N <= 4096;
 
-  static hipError_t spectra(const float2* h, int K, int M, float2* F, const float2* tw, hipStream_t st) {
+  static hipError_t spectra(const void* h, int K, int M, float2* F, const float2* tw, hipStream_t st, int diff,
+                            int real) {
     const int blocks = (K + GE::SEGS - 1) / GE::SEGS;
-    hipLaunchKernelGGL(ols_filter_spectra_kernel<N>, dim3(blocks), dim3(GE::WG), 0, st, h, K, M, F, tw);
+    hipLaunchKernelGGL(ols_filter_spectra_kernel<N>, dim3(blocks), dim3(GE::WG), 0, st, h, K, M, F, tw, diff, real);
     return hipGetLastError();
   }
   static hipError_t natural(const float2* F, int K, float2* out, hipStream_t st) {
@@ -525,28 +544,36 @@ struct Kern {
     hipLaunchKernelGGL(ols_spectra_natural_kernel<N>, dim3((unsigned)blocks), dim3(threads), 0, st, F, K, out);
     return hipGetLastError();
   }
+  // Forward kernel instance for (filters per unit, power epilogue, R2R).
+  using ForwardFn = void (*)(const void*, int64_t, const float2*, void*, int, int, int, int64_t, const float2*);
   template <int NF>
-  static hipError_t forward_nf(const ols_plan_s* p, const float2* s, int64_t Ns, float2* y, hipStream_t st) {
+  static ForwardFn forward_fn_nf(bool power, bool real) {
+    if (real) {
+      // R2R takes two filters per unit only up to N = 2048 (choose_nf_real)
+      constexpr int NFR = N <= BATCH_NF2_MAX_N ? NF : 1;
+      return power ? ols_forward_kernel<N, NFR, true, true> : ols_forward_kernel<N, NFR, false, true>;
+    }
+    return power ? ols_forward_kernel<N, NF, true, false> : ols_forward_kernel<N, NF, false, false>;
+  }
+  static ForwardFn forward_fn(int nf, int flags) {
+    const bool power = (flags & OLS_POST_POWER) != 0, real = (flags & OLS_REAL) != 0;
+    if constexpr (HAS_NF2) {
+      if (nf == 2) return forward_fn_nf<2>(power, real);
+    }
+    return forward_fn_nf<1>(power, real);
+  }
+  static hipError_t forward(const ols_plan_s* p, const void* s, int64_t Ns, void* y, hipStream_t st) {
     const int64_t nseg = (Ns + p->H - 1) / p->H;
-    const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
-    const int64_t units = ntiles * ((p->K + NF - 1) / NF);
+    const int64_t ntrans = (p->flags & OLS_REAL) ? (nseg + 1) / 2 : nseg;  // R2R: segment pairs
+    const int64_t ntiles = (ntrans + GE::SEGS - 1) / GE::SEGS;
+    const int64_t units = ntiles * ((p->K + p->nf - 1) / p->nf);
     const int64_t grid = units < p->grid ? units : p->grid;
-    hipLaunchKernelGGL((ols_forward_kernel<N, NF>), dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra, y,
+    hipLaunchKernelGGL(forward_fn(p->nf, p->flags), dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra, y,
                        p->K, p->D, p->H, ntiles, p->twiddles);
     return hipGetLastError();
   }
-  static hipError_t forward(const ols_plan_s* p, const float2* s, int64_t Ns, float2* y, hipStream_t st) {
-    if constexpr (HAS_NF2) {
-      if (p->nf == 2) return forward_nf<2>(p, s, Ns, y, st);
-    }
-    return forward_nf<1>(p, s, Ns, y, st);
-  }
-  static hipError_t occupancy(int nf, int* blocks_per_cu) {
-    if constexpr (HAS_NF2) {
-      if (nf == 2)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_forward_kernel<N, 2>, GE::WG, 0);
-    }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_forward_kernel<N, 1>, GE::WG, 0);
+  static hipError_t occupancy(int nf, int flags, int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, forward_fn(nf, flags), GE::WG, 0);
   }
   static hipError_t bwd_occupancy(int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_backward_kernel<N>, GE::WG, 0);
@@ -594,8 +621,8 @@ auto dispatch(int N, Args&&... args) -> decltype(F<256>::run(args...)) {
 
 template <int N>
 struct RunSpectra {
-  static hipError_t run(const float2* h, int K, int M, float2* F, const float2* tw, hipStream_t st) {
-    return Kern<N>::spectra(h, K, M, F, tw, st);
+  static hipError_t run(const void* h, int K, int M, float2* F, const float2* tw, hipStream_t st, int diff, int real) {
+    return Kern<N>::spectra(h, K, M, F, tw, st, diff, real);
   }
 };
 template <int N>
@@ -604,13 +631,13 @@ struct RunNatural {
 };
 template <int N>
 struct RunForward {
-  static hipError_t run(const ols_plan_s* p, const float2* s, int64_t Ns, float2* y, hipStream_t st) {
+  static hipError_t run(const ols_plan_s* p, const void* s, int64_t Ns, void* y, hipStream_t st) {
     return Kern<N>::forward(p, s, Ns, y, st);
   }
 };
 template <int N>
 struct RunOccupancy {
-  static hipError_t run(int nf, int* b) { return Kern<N>::occupancy(nf, b); }
+  static hipError_t run(int nf, int flags, int* b) { return Kern<N>::occupancy(nf, flags, b); }
 };
 template <int N>
 struct RunBwdOccupancy {
@@ -674,25 +701,34 @@ const char* ols_status_string(ols_status_t s) {
 const char* ols_last_error(void) { return g_last_error.c_str(); }
 
 ols_status_t ols_plan(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int32_t N, ols_stream_t stream) {
+  return ols_plan_ex(plan, h, K, M, N, OLS_POST_NONE, stream);
+}
+
+ols_status_t ols_plan_ex(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int32_t N, int32_t flags,
+                         ols_stream_t stream) {
   try {
     if (!plan) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
     *plan = nullptr;
     if (!h) return fail(OLS_ERROR_INVALID_VALUE, "h is NULL");
     if (K < 1) return fail(OLS_ERROR_INVALID_VALUE, "K must be >= 1");
     if (M < 1) return fail(OLS_ERROR_INVALID_VALUE, "M must be >= 1");
-    if (((uintptr_t)h) % 8) return fail(OLS_ERROR_INVALID_VALUE, "h must be 8-byte aligned");
+    if (flags & ~(OLS_POST_DERIVATIVE | OLS_POST_POWER | OLS_REAL)) return fail(OLS_ERROR_INVALID_VALUE, "unknown flag");
+    const int align = (flags & OLS_REAL) ? 4 : 8;
+    if (((uintptr_t)h) % align) return fail(OLS_ERROR_INVALID_VALUE, "h is not aligned to its element type");
+    // the derivative is a convolution with [1, -1]: one more tap of aliasing
+    const int Meff = (flags & OLS_POST_DERIVATIVE) ? M + 1 : M;
     if (N == 0) {
       double best = 1e301;
       for (int n = OLS_MIN_FFT_LENGTH; n <= OLS_MAX_FFT_LENGTH; n *= 2) {
-        if (n < M) continue;
-        const double c = cost_per_output(n, M, K);
+        if (n < Meff) continue;
+        const double c = cost_per_output(n, Meff, K);
         if (c < best) { best = c; N = n; }
       }
       if (N == 0) return fail(OLS_ERROR_INVALID_VALUE, "filter longer than the largest FFT length");
     }
     if (!is_pow2(N) || N < OLS_MIN_FFT_LENGTH || N > OLS_MAX_FFT_LENGTH)
       return fail(OLS_ERROR_UNSUPPORTED, "N must be a power of two in [256, 8192]");
-    if (M > N) return fail(OLS_ERROR_INVALID_VALUE, "M must be <= N");
+    if (Meff > N) return fail(OLS_ERROR_INVALID_VALUE, "M must be <= N (M + 1 <= N with the derivative)");
     if ((int64_t)K * N > ((int64_t)1 << 40)) return fail(OLS_ERROR_INVALID_VALUE, "K*N too large");
 
     ols_plan_s* p = new (std::nothrow) ols_plan_s();
@@ -700,15 +736,16 @@ ols_status_t ols_plan(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int
     p->K = K;
     p->M = M;
     p->N = N;
-    p->D = default_delay(N, M);
+    p->flags = flags;
+    p->D = default_delay(N, Meff);
     p->H = N - p->D;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipGetDevice"); }
     e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipDeviceGetAttribute"); }
-    p->nf = choose_nf(N, K);
+    p->nf = (flags & OLS_REAL) ? choose_nf_real(N, K) : choose_nf(N, K);
     int per_cu = 0;
-    e = dispatch<RunOccupancy>(N, p->nf, &per_cu);
+    e = dispatch<RunOccupancy>(N, p->nf, flags, &per_cu);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "occupancy query"); }
     if (per_cu < 1) per_cu = 1;
     p->grid = per_cu * p->cus;
@@ -723,7 +760,8 @@ ols_status_t ols_plan(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int
     hipStream_t st = (hipStream_t)stream;
     e = hipMemcpyAsync(p->twiddles, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "twiddle upload"); }
-    e = dispatch<RunSpectra>(N, (const float2*)h, K, M, p->spectra, (const float2*)p->twiddles, st);
+    e = dispatch<RunSpectra>(N, h, K, M, p->spectra, (const float2*)p->twiddles, st,
+                             (flags & OLS_POST_DERIVATIVE) ? 1 : 0, (flags & OLS_REAL) ? 1 : 0);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "filter spectra launch"); }
     e = hipStreamSynchronize(st);  // the host twiddle buffer and h are released after this
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "plan synchronisation"); }
@@ -737,9 +775,11 @@ ols_status_t ols_plan(ols_plan_t* plan, const void* h, int32_t K, int32_t M, int
 ols_status_t ols_plan_update_filters(ols_plan_t p, const void* h, ols_stream_t stream) {
   try {
     if (!p || !h) return fail(OLS_ERROR_INVALID_VALUE, "NULL argument");
-    if (((uintptr_t)h) % 8) return fail(OLS_ERROR_INVALID_VALUE, "h must be 8-byte aligned");
-    hipError_t e = dispatch<RunSpectra>(p->N, (const float2*)h, p->K, p->M, p->spectra,
-                                        (const float2*)p->twiddles, (hipStream_t)stream);
+    if (((uintptr_t)h) % ((p->flags & OLS_REAL) ? 4 : 8))
+      return fail(OLS_ERROR_INVALID_VALUE, "h is not aligned to its element type");
+    hipError_t e = dispatch<RunSpectra>(p->N, h, p->K, p->M, p->spectra, (const float2*)p->twiddles,
+                                        (hipStream_t)stream, (p->flags & OLS_POST_DERIVATIVE) ? 1 : 0,
+                                        (p->flags & OLS_REAL) ? 1 : 0);
     if (e != hipSuccess) return hip_fail(e, "filter spectra launch");
     return OLS_SUCCESS;
   } catch (...) {
@@ -749,14 +789,15 @@ ols_status_t ols_plan_update_filters(ols_plan_t p, const void* h, ols_stream_t s
 
 ols_status_t ols_plan_set_hop(ols_plan_t p, int32_t H) {
   if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
-  const int L = p->N - p->M + 1;
+  const int Meff = (p->flags & OLS_POST_DERIVATIVE) ? p->M + 1 : p->M;
+  const int L = p->N - Meff + 1;
   if (H == 0) {
-    p->D = default_delay(p->N, p->M);
+    p->D = default_delay(p->N, Meff);
     p->H = p->N - p->D;
     return OLS_SUCCESS;
   }
   if (H < 1 || H > L) return fail(OLS_ERROR_INVALID_VALUE, "hop must satisfy 1 <= H <= N-M+1");
-  int D = default_delay(p->N, p->M);
+  int D = default_delay(p->N, Meff);
   if (D + H > p->N) D = p->N - H;
   p->D = D;
   p->H = H;
@@ -801,12 +842,15 @@ ols_status_t ols_forward(ols_plan_t p, const void* s, int64_t Ns, void* y, ols_s
     if (Ns < 0) return fail(OLS_ERROR_INVALID_VALUE, "N_s must be >= 0");
     if (Ns == 0) return OLS_SUCCESS;
     if (!s || !y) return fail(OLS_ERROR_INVALID_VALUE, "s or y is NULL");
-    if (((uintptr_t)s) % 8 || ((uintptr_t)y) % 8) return fail(OLS_ERROR_INVALID_VALUE, "s and y must be 8-byte aligned");
+    const bool real = (p->flags & OLS_REAL) != 0;
+    const size_t s_el = real ? 4 : 8;                                       // sample size of s
+    const size_t y_el = (real || (p->flags & OLS_POST_POWER)) ? 4 : 8;     // sample size of y
+    if (((uintptr_t)s) % s_el || ((uintptr_t)y) % y_el)
+      return fail(OLS_ERROR_INVALID_VALUE, "s or y is not aligned to its element type");
     if (Ns > ((int64_t)1 << 56) / 8 / p->K) return fail(OLS_ERROR_INVALID_VALUE, "K*N_s*8 overflows");
-    if (ranges_overlap(s, (size_t)Ns * 8, y, (size_t)Ns * 8 * (size_t)p->K))
+    if (ranges_overlap(s, (size_t)Ns * s_el, y, (size_t)Ns * (size_t)p->K * y_el))
       return fail(OLS_ERROR_INVALID_VALUE, "y overlaps s (out of place only)");
-    hipError_t e = dispatch<RunForward>(p->N, (const ols_plan_s*)p, (const float2*)s, Ns, (float2*)y,
-                                        (hipStream_t)stream);
+    hipError_t e = dispatch<RunForward>(p->N, (const ols_plan_s*)p, s, Ns, y, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return OLS_SUCCESS;
   } catch (...) {
@@ -845,6 +889,7 @@ ols_status_t ols_backward(ols_plan_t p, const void* s, int64_t Ns, const void* g
                           ols_stream_t stream) {
   try {
     if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+    if (p->flags != OLS_POST_NONE) return fail(OLS_ERROR_UNSUPPORTED, "backward of a post-processed or R2R plan");
     if (Ns < 0) return fail(OLS_ERROR_INVALID_VALUE, "N_s must be >= 0");
     if (!ds && !dh) return OLS_SUCCESS;
     if (dh && !s && Ns > 0) return fail(OLS_ERROR_INVALID_VALUE, "s is needed for dh");
@@ -957,7 +1002,7 @@ ols_status_t ols_batch_plan(ols_batch_t* out, const ols_batch_item_t* items, int
       d.spectra = F;
       off += (size_t)d.K * d.N;
       const int k = ilog2(d.N) - 8;
-      e = dispatch<RunSpectra>(d.N, (const float2*)items[i].h, d.K, d.M, F, (const float2*)b->tw[k], st);
+      e = dispatch<RunSpectra>(d.N, items[i].h, d.K, d.M, F, (const float2*)b->tw[k], st, 0, 0);
       if (e != hipSuccess) { destroy_batch(b); return hip_fail(e, "filter spectra launch"); }
     }
     if (hipMalloc(&b->items_dev, (size_t)n * sizeof(BatchItem)) != hipSuccess) { destroy_batch(b); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "item table allocation"); }

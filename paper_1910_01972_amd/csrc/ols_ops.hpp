@@ -35,6 +35,57 @@ OLS_HD void load_filter(float2 (&x)[16], const float2* __restrict__ h, int M, bo
   }
 }
 
+// Filter r followed by a first difference, h'[k] = h[k] - h[k-1] for
+// k = 0 .. M (h[-1] = h[M] = 0): y' = y * [1, -1] is the derivative of the
+// convolved signal (sec. 4, non-local post-processing) and, being a
+// convolution, it folds into the filter spectrum at no cost per segment.
+template <int N>
+OLS_HD void load_filter_diff(float2 (&x)[16], const float2* __restrict__ h, int M, bool valid, int g) {
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int p = g + time_pos_const<N>(reg);
+    const float2 a = (valid && p < M) ? h[p] : make_float2(0.f, 0.f);
+    const float2 b = (valid && p >= 1 && p <= M) ? h[p - 1] : make_float2(0.f, 0.f);
+    x[reg] = csub(a, b);
+  }
+}
+
+// Real filter r (R2R plans) as complex taps with zero imaginary part,
+// optionally followed by the first difference of load_filter_diff.
+template <int N>
+OLS_HD void load_filter_real(float2 (&x)[16], const float* __restrict__ h, int M, bool valid, bool diff, int g) {
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int p = g + time_pos_const<N>(reg);
+    float a = (valid && p < M) ? h[p] : 0.f;
+    if (diff) a -= (valid && p >= 1 && p <= M) ? h[p - 1] : 0.f;
+    x[reg] = make_float2(a, 0.f);
+  }
+}
+
+// Two real segments in one complex transform (R2R): segment 2q in the real
+// part, segment 2q+1 in the imaginary part.  With real filters the product
+// of their joint spectrum with a filter spectrum transforms back to the two
+// real convolutions in the real and imaginary parts, so the pair costs one
+// complex FFT of length N and needs no split of the spectra.  start is the
+// window start of segment 2q; segment 2q+1 starts H samples later.
+template <int N>
+OLS_HD void load_segment_pair(float2 (&x)[16], const float* __restrict__ s, int64_t Ns, int64_t start, int H, int g) {
+  const int64_t lo0 = -start, hi0 = Ns - start;
+  const int lo_a = lo0 <= 0 ? 0 : (lo0 >= N ? N : (int)lo0);
+  const int hi_a = hi0 <= 0 ? 0 : (hi0 >= N ? N : (int)hi0);
+  const int64_t lo1 = lo0 - H, hi1 = hi0 - H;
+  const int lo_b = lo1 <= 0 ? 0 : (lo1 >= N ? N : (int)lo1);
+  const int hi_b = hi1 <= 0 ? 0 : (hi1 >= N ? N : (int)hi1);
+  const float* sa = s + start;
+  const float* sb = sa + H;
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int p = g + time_pos_const<N>(reg);
+    x[reg] = make_float2((p >= lo_a && p < hi_a) ? sa[p] : 0.f, (p >= lo_b && p < hi_b) ? sb[p] : 0.f);
+  }
+}
+
 // Spectra are stored in the order the forward transform leaves them in
 // registers: F[r][reg][g] (coalesced for every reg).
 template <int N>
@@ -129,12 +180,50 @@ OLS_HD void zero_lags(float2* __restrict__ part, int M, int g) {
   }
 }
 
+// Per-element post-processing at the store (sec. 4): the power |y|^2 as
+// float32, half the output bytes of complex64.
+template <int N>
+OLS_HD void store_valid_power(const float2 (&x)[16], float* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H,
+                              int g) {
+  const int64_t lim64 = Ns - out0 + D;
+  const int lim_n = lim64 >= D + H ? D + H : (int)(lim64 < 0 ? 0 : lim64);
+  float* base = yrow + (out0 - D);
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int p = g + time_pos_const<N>(reg);
+    if (p >= D && p < lim_n) base[p] = fmaf(x[reg].x, x[reg].x, x[reg].y * x[reg].y);
+  }
+}
+
+// Store of a segment pair (R2R): the real part holds segment 2q's output,
+// written from out0 = 2q*H, the imaginary part segment 2q+1's, written from
+// out0 + H; each with its own end bound.  POWER squares each sample.
+template <int N, bool POWER>
+OLS_HD void store_valid_pair(const float2 (&x)[16], float* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H,
+                             int g) {
+  const int64_t lim_a64 = Ns - out0 + D, lim_b64 = lim_a64 - H;
+  const int lim_a = lim_a64 >= D + H ? D + H : (int)(lim_a64 < 0 ? 0 : lim_a64);
+  const int lim_b = lim_b64 >= D + H ? D + H : (int)(lim_b64 < 0 ? 0 : lim_b64);
+  float* base = yrow + (out0 - D);
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int p = g + time_pos_const<N>(reg);
+    const float a = POWER ? x[reg].x * x[reg].x : x[reg].x;
+    const float b = POWER ? x[reg].y * x[reg].y : x[reg].y;
+    if (p >= D && p < lim_a) base[p] = a;
+    if (p >= D && p < lim_b) base[H + p] = b;
+  }
+}
+
 // Filters per work unit of the forward kernels: two interleaved transforms when
 // registers allow it (N <= 4096) and the filter count wastes little on a
 // padded last group; the batched kernel allows two only up to N = 2048.
 constexpr int BATCH_NF2_MAX_N = 2048;
 OLS_HD int choose_nf(int N, int K) { return (N <= 4096 && (K % 2 == 0 || K >= 9)) ? 2 : 1; }
 OLS_HD int choose_nf_batched(int N, int K) { return N <= BATCH_NF2_MAX_N ? choose_nf(N, K) : 1; }
+// R2R (segment pairs) needs a few more registers per transform: two filters
+// per unit only up to N = 2048 as well.
+OLS_HD int choose_nf_real(int N, int K) { return N <= BATCH_NF2_MAX_N ? choose_nf(N, K) : 1; }
 
 // Partition arithmetic shared by the persistent kernels: workgroup b of P
 // owns units [first_unit(b), first_unit(b+1)); owner(u) inverts it.

@@ -22,6 +22,8 @@ def emu() -> ctypes.CDLL:
         L = ctypes.CDLL(EMU_PATH)
         P, I32, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
         L.ols_emu_forward.argtypes = [I32, P, I64, P, I32, I32, I32, I32, I32, P]
+        L.ols_emu_forward_post.argtypes = [I32, P, I64, P, I32, I32, I32, I32, I32, I32, P]
+        L.ols_emu_forward_post.restype = I32
         L.ols_emu_spectra.argtypes = [I32, P, I32, I32, P]
         L.ols_emu_lds_report.argtypes = [I32, P]
         L.ols_emu_geometry.argtypes = [I32, P]
@@ -82,6 +84,29 @@ def forward(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, gua
     y_guard_ok = bool(np.all(np.isnan(ybuf[:guard])) and np.all(np.isnan(ybuf[guard + K * Ns:])))
     s_guard_ok = bool(np.all(np.isnan(sbuf[:guard])) and np.all(np.isnan(sbuf[guard + Ns:])))
     return y, s_guard_ok, y_guard_ok
+
+
+def forward_post(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, post: int, guard: int = 4096):
+    """Forward OLS with flags (1 derivative, 2 power, 4 R2R with float32 s, h
+    and y); the output is complex64 [K][N_s], or float32 for power and R2R,
+    inside NaN guard bands.  Returns (y, y_guard_ok)."""
+    real = bool(post & 4)
+    cdt = np.float32 if real else np.complex64
+    h = np.ascontiguousarray(h, dtype=cdt)
+    s = np.ascontiguousarray(s, dtype=cdt)
+    K, M = h.shape
+    Ns = int(s.shape[0])
+    dt, esz = (np.float32, 4) if post & 6 else (np.complex64, 8)
+    # the signal sits between NaN bands: a read outside [0, N_s) poisons the output
+    sbuf = np.full(Ns + 2 * guard, np.nan, dtype=cdt)
+    sbuf[guard:guard + Ns] = s
+    ybuf = np.full(K * Ns + 2 * guard, np.nan, dtype=dt)
+    rc = emu().ols_emu_forward_post(N, ctypes.c_void_p(sbuf.ctypes.data + guard * sbuf.itemsize), Ns, _ptr(h), K, M,
+                                    D, H, grid, int(post), ctypes.c_void_p(ybuf.ctypes.data + guard * esz))
+    if rc != 0:
+        raise RuntimeError(f"emulator returned {rc}")
+    ok = bool(np.all(np.isnan(ybuf[:guard])) and np.all(np.isnan(ybuf[guard + K * Ns:])))
+    return ybuf[guard:guard + K * Ns].reshape(K, Ns).copy(), ok
 
 
 def backward(s: np.ndarray, gy: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, guard: int = 4096):

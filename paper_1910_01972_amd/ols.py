@@ -11,7 +11,7 @@ import ctypes
 
 import torch
 
-from ._lib import check, lib
+from ._lib import OLSError, check, lib  # noqa: F401  (OLSError re-exported)
 
 
 def _stream_handle(stream) -> ctypes.c_void_p:
@@ -20,11 +20,11 @@ def _stream_handle(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _check_c64(t: torch.Tensor, name: str, ndim: int) -> None:
+def _check_c64(t: torch.Tensor, name: str, ndim: int, dtype=torch.complex64) -> None:
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
-    if t.dtype != torch.complex64:
-        raise TypeError(f"{name} must be complex64, got {t.dtype}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if t.device.type != "cuda":
         raise ValueError(f"{name} must be on a GPU device")
     if t.dim() != ndim:
@@ -37,16 +37,25 @@ class OLSPlan:
     """Filter bank h[K][M] (complex64, on the GPU) prepared for FFT length N.
 
     N = 0 lets the library choose.  The plan owns the filter spectra.
+    derivative / power select the fused post-processing of sec. 4: the
+    backward first difference of each output row (folded into the spectra)
+    and the per-element power |y|^2 (float32 output).  A float32 filter bank
+    makes a real-to-real (R2R) plan: the signal and the output are float32.
     """
 
-    def __init__(self, h: torch.Tensor, N: int = 0, stream=None):
-        _check_c64(h, "h", 2)
+    def __init__(self, h: torch.Tensor, N: int = 0, stream=None, derivative: bool = False, power: bool = False):
+        self.real = isinstance(h, torch.Tensor) and h.dtype == torch.float32
+        self._in_dtype = torch.float32 if self.real else torch.complex64
+        _check_c64(h, "h", 2, self._in_dtype)
         self._handle = ctypes.c_void_p()
         self.K, self.M = int(h.shape[0]), int(h.shape[1])
         self.device = h.device
+        self.post = (1 if derivative else 0) | (2 if power else 0)
+        self.flags = self.post | (4 if self.real else 0)
+        self._out_dtype = torch.float32 if (self.real or power) else torch.complex64
         with torch.cuda.device(h.device):
-            check(lib().ols_plan(ctypes.byref(self._handle), ctypes.c_void_p(h.data_ptr()), self.K, self.M, int(N),
-                                 _stream_handle(stream)), "ols_plan")
+            check(lib().ols_plan_ex(ctypes.byref(self._handle), ctypes.c_void_p(h.data_ptr()), self.K, self.M, int(N),
+                                    self.flags, _stream_handle(stream)), "ols_plan_ex")
 
     def __del__(self):
         self.close()
@@ -77,7 +86,7 @@ class OLSPlan:
         check(lib().ols_plan_set_hop(self.handle, int(H)), "ols_plan_set_hop")
 
     def update_filters(self, h: torch.Tensor, stream=None) -> None:
-        _check_c64(h, "h", 2)
+        _check_c64(h, "h", 2, self._in_dtype)
         if tuple(h.shape) != (self.K, self.M):
             raise ValueError("filter bank shape must stay (K, M)")
         check(lib().ols_plan_update_filters(self.handle, ctypes.c_void_p(h.data_ptr()), _stream_handle(stream)),
@@ -92,13 +101,16 @@ class OLSPlan:
         return out
 
     def forward(self, s: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """y[K][N_s] = eq. (1) of s with every filter (zero history)."""
-        _check_c64(s, "s", 1)
+        """y[K][N_s] = eq. (1) of s with every filter (zero history),
+        post-processed as the plan's flags say."""
+        _check_c64(s, "s", 1, self._in_dtype)
         Ns = int(s.shape[0])
+        out_dtype = self._out_dtype
         if y is None:
-            y = torch.empty((self.K, Ns), dtype=torch.complex64, device=s.device)
+            y = torch.empty((self.K, Ns), dtype=out_dtype, device=s.device)
         else:
-            _check_c64(y, "y", 2)
+            if y.dtype != out_dtype or y.device.type != "cuda" or not y.is_contiguous():
+                raise ValueError(f"y must be a contiguous {out_dtype} GPU tensor")
             if tuple(y.shape) != (self.K, Ns):
                 raise ValueError("y must have shape (K, N_s)")
         check(lib().ols_forward(self.handle, ctypes.c_void_p(s.data_ptr()), Ns, ctypes.c_void_p(y.data_ptr()),
@@ -228,9 +240,11 @@ class OLSBatch:
         self.close()
 
 
-def ols_conv(s: torch.Tensor, h: torch.Tensor, N: int = 0, stream=None) -> torch.Tensor:
-    """One-shot overlap-and-save convolution: y[K][N_s]."""
-    plan = OLSPlan(h, N=N, stream=stream)
+def ols_conv(s: torch.Tensor, h: torch.Tensor, N: int = 0, stream=None, derivative: bool = False,
+             power: bool = False) -> torch.Tensor:
+    """One-shot overlap-and-save convolution: y[K][N_s] (post-processed as
+    OLSPlan's flags select)."""
+    plan = OLSPlan(h, N=N, stream=stream, derivative=derivative, power=power)
     try:
         return plan.forward(s, stream=stream)
     finally:

@@ -5,7 +5,7 @@ without a GPU (the GPU parity tests repeat the comparison on the device)."""
 import numpy as np
 import pytest
 
-from oracle import conv
+from oracle import conv, post
 import workloads
 
 emu = pytest.importorskip("paper_1910_01972_amd.emu")
@@ -157,3 +157,76 @@ def test_batched_walk_vs_oracle():
                 continue
             assert not np.isnan(y).any()
             assert np.all(_rel(y, conv.direct_conv(it["s"], it["h"])) <= 1e-5)
+
+
+POST_CASES = [
+    # (Ns, K, M, N, post): 1 derivative, 2 power, 3 power of the derivative
+    (3000, 3, 40, 256, 1),
+    (3000, 3, 40, 256, 2),
+    (5000, 2, 255, 256, 1),     # M + 1 = N: the derivative fills the segment's history
+    (9000, 4, 100, 1024, 3),
+    (20000, 5, 513, 2048, 1),
+    (20000, 6, 300, 2048, 2),
+    (30000, 3, 1000, 4096, 3),
+    (40000, 2, 700, 8192, 1),
+    (1, 2, 1, 512, 3),
+]
+
+
+@pytest.mark.parametrize("Ns,K,M,N,post_flags", POST_CASES)
+def test_post_processing_vs_oracle(Ns, K, M, N, post_flags):
+    """Derivative folded into the spectra and the power epilogue at the store
+    (sec. 4) through the kernel dataflow, against the oracle's definitions."""
+    s, h = workloads.make_signal_filters(Ns, K, M, seed=Ns + M)
+    Meff = M + 1 if post_flags & 1 else M
+    D = default_delay(N, Meff)
+    y, ok = emu.forward_post(s, h, N, D, N - D, grid=7, post=post_flags)
+    assert ok and not np.isnan(y).any()
+    ref = conv.direct_conv(s, h)
+    if post_flags & 1:
+        ref = post.derivative(ref)
+    if post_flags & 2:
+        ref = post.power(ref)
+        assert y.dtype == np.float32
+    assert np.all(_rel(y, ref) <= 1e-5), _rel(y, ref)
+
+
+REAL_CASES = [
+    # (Ns, K, M, N, flags): R2R, two real segments per complex transform
+    (1, 1, 1, 256, 4),
+    (255, 2, 3, 256, 4),           # fewer samples than one segment
+    (3000, 3, 40, 256, 4),
+    (3001, 4, 40, 256, 4),         # odd segment count: the last pair is half empty
+    (9000, 4, 100, 1024, 4 | 2),
+    (20000, 5, 513, 2048, 4),
+    (20000, 6, 300, 2048, 4 | 1),
+    (30000, 3, 1000, 4096, 4),
+    (40000, 2, 700, 8192, 4 | 1 | 2),
+    (50000, 9, 64, 512, 4),
+]
+
+
+@pytest.mark.parametrize("Ns,K,M,N,flags", REAL_CASES)
+def test_real_to_real_vs_oracle(Ns, K, M, N, flags):
+    s, h = workloads.make_real_signal_filters(Ns, K, M, seed=Ns + 3 * M)
+    Meff = M + 1 if flags & 1 else M
+    D = default_delay(N, Meff)
+    y, ok = emu.forward_post(s, h, N, D, N - D, grid=7, post=flags)
+    assert ok and not np.isnan(y).any()
+    assert y.dtype == np.float32
+    ref = conv.direct_conv_real(s, h)
+    if flags & 1:
+        ref = post.derivative(ref).real
+    if flags & 2:
+        ref = ref * ref
+    assert np.all(_rel(y, ref) <= 1e-5), _rel(y, ref)
+
+
+def test_real_to_real_hop_invariance():
+    s, h = workloads.make_real_signal_filters(7000, 3, 100, seed=77)
+    ref = conv.direct_conv_real(s, h)
+    for N, H in ((256, 157), (256, 1), (512, 300), (1024, 925)):
+        D = N - H
+        assert D >= 99
+        y, ok = emu.forward_post(s, h, N, D, H, grid=5, post=4)
+        assert ok and np.all(_rel(y, ref) <= 1e-5), (N, H)

@@ -1,0 +1,139 @@
+"""GPU parity of the fused post-processing (sec. 4): the derivative folded
+into the filter spectra and the power epilogue at the store, against the
+oracle's definitions (bar: relative L2 error <= 1e-5 per filter row)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import conv, post  # noqa: E402
+import workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+GUARD = 4096
+
+
+@pytest.fixture(scope="module")
+def ols():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_01972_amd import ols as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def rel_rows(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+def reference(s, h, derivative, power):
+    y = conv.direct_conv(s, h)
+    if derivative:
+        y = post.derivative(y)
+    if power:
+        y = post.power(y)
+    return y
+
+
+CASES = [
+    # (Ns, K, M, N, derivative, power)
+    (1, 1, 1, 256, True, True),
+    (5000, 3, 40, 256, True, False),
+    (5000, 3, 40, 256, False, True),
+    (7000, 2, 255, 256, True, False),      # M + 1 = N
+    (20000, 4, 100, 1024, True, True),
+    (65536, 32, 256, 2048, False, True),
+    (65536, 9, 513, 2048, True, False),
+    (30000, 3, 1000, 4096, True, True),
+    (40000, 2, 2000, 8192, True, False),
+    (100001, 16, 64, 512, False, True),
+]
+
+
+@pytest.mark.parametrize("Ns,K,M,N,derivative,power", CASES)
+def test_post_full(ols, Ns, K, M, N, derivative, power):
+    say(f"post Ns={Ns} K={K} M={M} N={N} derivative={derivative} power={power}")
+    s, h = workloads.make_signal_filters(Ns, K, M, seed=Ns + K)
+    plan = ols.OLSPlan(dev(h), N=N, derivative=derivative, power=power)
+    dt = torch.float32 if power else torch.complex64
+    fill = float("nan") if power else complex(float("nan"), float("nan"))
+    buf = torch.full((K * Ns + 2 * GUARD,), fill, dtype=dt, device="cuda")
+    y = buf[GUARD:GUARD + K * Ns].view(K, Ns)
+    plan.forward(dev(s), y=y)
+    torch.cuda.synchronize()
+    b = buf.cpu().numpy()
+    assert np.isnan(b[:GUARD]).all() and np.isnan(b[GUARD + K * Ns:]).all(), "guard band written"
+    got = y.cpu().numpy()
+    assert not np.isnan(got).any()
+    r = rel_rows(got, reference(s, h, derivative, power))
+    assert np.all(r <= TOL), r
+    plan.close()
+
+
+def test_post_hop_bounds_and_update(ols):
+    """The derivative adds one aliased sample: the hop may reach N - M, not
+    N - M + 1; replacing the filters keeps the post-processing."""
+    Ns, K, M, N = 12000, 3, 100, 512
+    s, h = workloads.make_signal_filters(Ns, K, M, seed=61)
+    plan = ols.OLSPlan(dev(h), N=N, derivative=True)
+    with pytest.raises(ols.OLSError):
+        plan.set_hop(N - M + 1)
+    plan.set_hop(N - M)
+    got = plan.forward(dev(s)).cpu().numpy()
+    assert np.all(rel_rows(got, reference(s, h, True, False)) <= TOL)
+    _, h2 = workloads.make_signal_filters(1, K, M, seed=62)
+    plan.update_filters(dev(h2))
+    plan.set_hop(0)
+    got = plan.forward(dev(s)).cpu().numpy()
+    assert np.all(rel_rows(got, reference(s, h2, True, False)) <= TOL)
+    with pytest.raises(ols.OLSError):
+        ols.OLSPlan(dev(workloads.make_signal_filters(1, 1, 256, seed=1)[1]), N=256, derivative=True)
+    plan.close()
+
+
+def test_post_plan_refuses_backward_and_bad_output(ols):
+    s, h = workloads.make_signal_filters(3000, 2, 30, seed=63)
+    plan = ols.OLSPlan(dev(h), N=256, power=True)
+    with pytest.raises(ols.OLSError):
+        plan.backward(dev(s), dev(workloads.make_grad(2, 3000, seed=63)))
+    with pytest.raises(ValueError):
+        plan.forward(dev(s), y=torch.empty((2, 3000), dtype=torch.complex64, device="cuda"))
+    plan.close()
+
+
+def test_post_full_size_sampled(ols):
+    """The 2^23-sample, 32-filter, 256-tap filter bank at N = 2048 with the
+    power epilogue and with the derivative: sampled outputs against the oracle
+    evaluated one by one (eq. 1 is local), including segment edges."""
+    wl = workloads.WORKLOADS["filter_bank_2p23_k32_m256"]
+    s, h = workloads.make_signal_filters(wl.Ns, wl.K, wl.M, seed=wl.seed)
+    sd = dev(s)
+    rng = np.random.default_rng(71)
+    for derivative, power in ((False, True), (True, False)):
+        say(f"full-size sampled derivative={derivative} power={power}")
+        plan = ols.OLSPlan(dev(h), N=wl.N, derivative=derivative, power=power)
+        H = plan.info()["H"]
+        idx = np.unique(np.concatenate([np.arange(0, 700), np.arange(wl.Ns - 300, wl.Ns)] +
+                                       [np.arange(j * H - 2, j * H + 2) for j in rng.integers(1, wl.Ns // H, 64)] +
+                                       [rng.integers(0, wl.Ns, 2000)]))
+        y = plan.forward(sd)
+        got = y[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+        del y
+        if derivative:
+            ref = post.derivative_at(s, h, idx)
+        else:
+            ref = post.power(conv.direct_conv_at(s, h, idx))
+        assert np.all(rel_rows(got, ref) <= TOL), rel_rows(got, ref)
+        plan.close()
