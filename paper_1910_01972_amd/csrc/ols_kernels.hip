@@ -151,7 +151,7 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
 // REAL (R2R): s and y are float32 and a transform carries a pair of segments
 // (real part 2q, imaginary part 2q+1), so a tile is SEGS pairs.  POWER
 // stores |y|^2 (float32) instead of y.
-template <int N, int NF, bool POWER = false, bool REAL = false>
+template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_BUFFER>
 __device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2* __restrict__ twt, int64_t u0, int64_t u1, float2* lds,
@@ -208,9 +208,12 @@ __device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64
     for (int f = 0; f < NF; ++f) {
       const int r = rg * NF + f;
       if (NF == 1 || r < K) {
-        if constexpr (REAL) store_valid_pair<N, POWER>(x[f], (float*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
-        else if constexpr (POWER) store_valid_power<N>(x[f], (float*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
-        else store_valid<N>(x[f], (float2*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
+        if constexpr (REAL)
+          store_valid_pair<N, POWER, SMODE>(x[f], (float*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
+        else if constexpr (POWER)
+          store_valid_power<N, SMODE>(x[f], (float*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
+        else
+          store_valid<N, SMODE>(x[f], (float2*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
       }
     }
     ++rg;
@@ -259,7 +262,7 @@ struct BatchItem {
 template <int N, int NF>
 __device__ __attribute__((noinline)) void batched_item_range(const BatchItem& it, const float2* twt, int64_t a,
                                                              int64_t b, float2* lds, int& par) {
-  forward_range<N, NF, false>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, twt, a, b, lds, par);
+  forward_range<N, NF, false, false, STORE_NT>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, twt, a, b, lds, par);
 }
 
 // Two filters per unit only up to N = 2048 here (BATCH_NF2_MAX_N): the
