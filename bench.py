@@ -243,6 +243,9 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the side measurements (adjoint, batched, variants), so that a profile of this "
+                         "run holds only the benchmark's launches")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run the library's plain copy kernel on MIB MiB "
@@ -340,9 +343,10 @@ def main():
     plan.close()
     del y
     torch.cuda.empty_cache()
-    rec["fwd_bwd"] = fwd_bwd_measurement(min(args.steps, 100), min(args.warmup, 50))
-    rec["batched"] = batched_measurement(max(3, min(args.steps, 200) // 20), 3)
-    rec["variants"] = variants_measurement(min(args.steps, 100), min(args.warmup, 50))
+    if not args.no_side:
+        rec["fwd_bwd"] = fwd_bwd_measurement(min(args.steps, 100), min(args.warmup, 50))
+        rec["batched"] = batched_measurement(max(3, min(args.steps, 200) // 20), 3)
+        rec["variants"] = variants_measurement(min(args.steps, 100), min(args.warmup, 50))
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(s_np, h_np, args.cpu_sample)
     print(json.dumps(rec), flush=True)
