@@ -180,8 +180,9 @@ ols_status_t ols_forward(ols_plan_t plan, const void* s, int64_t N_s, void* y, o
 ols_status_t ols_backward(ols_plan_t plan, const void* s, int64_t N_s, const void* gy, void* ds, void* dh,
                           ols_stream_t stream);
 
-/* Allocate the plan's backward workspace now (grid x 2 x SEGS x N and
- * grid x SEGS x K x M complex64, grid = persistent workgroups), so that
+/* Allocate the plan's backward workspace now (grid x 2 x SEGS x N,
+ * grid x SEGS x K x M and ceil(grid x SEGS / 16) x K x M complex64,
+ * grid = persistent workgroups), so that
  * ols_backward never allocates.  Idempotent.  Errors: INVALID_VALUE,
  * OUT_OF_MEMORY, HIP. */
 ols_status_t ols_plan_reserve_backward(ols_plan_t plan);

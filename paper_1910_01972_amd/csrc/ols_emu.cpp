@@ -335,10 +335,15 @@ int backward(const float2* s, int64_t Ns, const float2* gy, const float2* h, int
       ds[o] = a;
     }
   }
-  const int64_t KM = (int64_t)K * M;
+  const int64_t KM = (int64_t)K * M, nslots = P * GE::SEGS, nch = dh_chunks(nslots);
   for (int64_t i = 0; i < KM; ++i) {
     float2 a = make_float2(0.f, 0.f);
-    for (int64_t sl = 0; sl < P * GE::SEGS; ++sl) a = cadd(a, part[sl * KM + i]);
+    for (int64_t c = 0; c < nch; ++c) {
+      float2 cs = make_float2(0.f, 0.f);
+      for (int64_t sl = c * DH_CHUNK; sl < std::min<int64_t>(nslots, (c + 1) * DH_CHUNK); ++sl)
+        cs = cadd(cs, part[sl * KM + i]);
+      a = cadd(a, cs);
+    }
     dh[i] = a;
   }
   return G.guards_ok() ? 0 : 3;

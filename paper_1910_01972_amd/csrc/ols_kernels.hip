@@ -440,7 +440,21 @@ __global__ void ols_ds_fixup_kernel(const float2* __restrict__ ws_ds, float2* __
   }
 }
 
-// dh[i] = sum over workgroup slots of part[slot][i], in slot order.
+// First level of the dh reduction: sums[c][i] = sum of part[slot][i] over
+// the slots of chunk c = blockIdx.y, in slot order.
+__global__ void ols_dh_chunk_kernel(const float2* __restrict__ part, int64_t nslots, int64_t KM,
+                                    float2* __restrict__ sums) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= KM) return;
+  const int64_t c = blockIdx.y;
+  const int64_t s0 = c * DH_CHUNK, s1 = s0 + DH_CHUNK < nslots ? s0 + DH_CHUNK : nslots;
+  float2 a = make_float2(0.f, 0.f);
+  for (int64_t sl = s0; sl < s1; ++sl) a = cadd(a, part[sl * KM + i]);
+  sums[c * KM + i] = a;
+}
+
+// dh[i] = sum over slots of part[slot][i], in slot order (second level: the
+// chunk sums in chunk order).
 __global__ void ols_dh_reduce_kernel(const float2* __restrict__ part, int64_t nslots, int64_t KM,
                                      float2* __restrict__ dh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -481,6 +495,7 @@ struct ols_plan_s {
   int bwd_grid = 0;           // persistent workgroups of the adjoint kernel
   float2* ws_ds = nullptr;    // [bwd_grid][2][SEGS][N] partial ds windows
   float2* part_dh = nullptr;  // [bwd_grid][SEGS][K][M] dh lag partials
+  float2* sum_dh = nullptr;   // [dh_chunks(bwd_grid * SEGS)][K][M] chunk sums of part_dh
   float2* spectra = nullptr;
   float2* twiddles = nullptr;
 };
@@ -599,8 +614,13 @@ struct Kern {
     }
     if (dh) {
       const int64_t KM = (int64_t)p->K * p->M;
-      hipLaunchKernelGGL(ols_dh_reduce_kernel, dim3((unsigned)((KM + 255) / 256)), dim3(256), 0, st, p->part_dh,
-                         grid * GE::SEGS, KM, dh);
+      const int64_t nslots = grid * GE::SEGS, nch = dh_chunks(nslots);
+      const unsigned bx = (unsigned)((KM + 255) / 256);
+      hipLaunchKernelGGL(ols_dh_chunk_kernel, dim3(bx, (unsigned)nch), dim3(256), 0, st, p->part_dh, nslots, KM,
+                         p->sum_dh);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(ols_dh_reduce_kernel, dim3(bx), dim3(256), 0, st, p->sum_dh, nch, KM, dh);
       e = hipGetLastError();
     }
     return e;
@@ -680,6 +700,7 @@ void destroy_plan(ols_plan_s* p) {
   if (!p) return;
   if (p->ws_ds) (void)hipFree(p->ws_ds);
   if (p->part_dh) (void)hipFree(p->part_dh);
+  if (p->sum_dh) (void)hipFree(p->sum_dh);
   if (p->spectra) (void)hipFree(p->spectra);
   if (p->twiddles) (void)hipFree(p->twiddles);
   delete p;
@@ -864,7 +885,7 @@ ols_status_t ols_forward(ols_plan_t p, const void* s, int64_t Ns, void* y, ols_s
 ols_status_t ols_plan_reserve_backward(ols_plan_t p) {
   try {
     if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
-    if (p->ws_ds && p->part_dh) return OLS_SUCCESS;
+    if (p->ws_ds && p->part_dh && p->sum_dh) return OLS_SUCCESS;
     int per_cu = 0;
     hipError_t e = dispatch<RunBwdOccupancy>(p->N, &per_cu);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
@@ -872,16 +893,18 @@ ols_status_t ols_plan_reserve_backward(ols_plan_t p) {
     const int grid = per_cu * p->cus;
     const size_t ws = (size_t)grid * 2 * p->segs * p->N * sizeof(float2);
     const size_t part = (size_t)grid * p->segs * p->K * p->M * sizeof(float2);
-    float2 *a = nullptr, *b = nullptr;
-    if (hipMalloc(&a, ws) != hipSuccess) { (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "backward workspace"); }
-    if (hipMalloc(&b, part) != hipSuccess) {
-      (void)hipFree(a);
+    const size_t sums = (size_t)dh_chunks((int64_t)grid * p->segs) * p->K * p->M * sizeof(float2);
+    float2 *a = nullptr, *b = nullptr, *c = nullptr;
+    if (hipMalloc(&a, ws) != hipSuccess || hipMalloc(&b, part) != hipSuccess || hipMalloc(&c, sums) != hipSuccess) {
+      if (a) (void)hipFree(a);
+      if (b) (void)hipFree(b);
       (void)hipGetLastError();
       return fail(OLS_ERROR_OUT_OF_MEMORY, "backward workspace");
     }
     p->bwd_grid = grid;
     p->ws_ds = a;
     p->part_dh = b;
+    p->sum_dh = c;
     return OLS_SUCCESS;
   } catch (...) {
     return fail(OLS_ERROR_INTERNAL, "exception in ols_plan_reserve_backward");
@@ -914,7 +937,7 @@ ols_status_t ols_backward(ols_plan_t p, const void* s, int64_t Ns, const void* g
       }
       return OLS_SUCCESS;
     }
-    if (!p->ws_ds || !p->part_dh) {
+    if (!p->ws_ds || !p->part_dh || !p->sum_dh) {
       const ols_status_t r = ols_plan_reserve_backward(p);
       if (r != OLS_SUCCESS) return r;
     }

@@ -311,6 +311,12 @@ OLS_HD int choose_nf_batched(int N, int K) { return N <= BATCH_NF2_MAX_N ? choos
 // per unit only up to N = 2048 as well.
 OLS_HD int choose_nf_real(int N, int K) { return N <= BATCH_NF2_MAX_N ? choose_nf(N, K) : 1; }
 
+// dh reduction order: the per-slot partial lags are summed in chunks of
+// DH_CHUNK consecutive slots (each chunk in slot order, one thread per lag
+// and chunk), then the chunk sums in chunk order.  Fixed order, no atomics.
+constexpr int DH_CHUNK = 16;
+OLS_HD int64_t dh_chunks(int64_t nslots) { return (nslots + DH_CHUNK - 1) / DH_CHUNK; }
+
 // Partition arithmetic shared by the persistent kernels: workgroup b of P
 // owns units [first_unit(b), first_unit(b+1)); owner(u) inverts it.
 OLS_HD int64_t first_unit(int64_t U, int64_t P, int64_t b) { return U * b / P; }
