@@ -262,6 +262,28 @@ ols_status_t ols_calibration_copy(void* dst, const void* src, size_t bytes, ols_
  * the persistent grid (workgroups) ols_forward launches for this plan. */
 ols_status_t ols_plan_get_launch(ols_plan_t plan, int32_t* grid, int32_t* block, int32_t* cus);
 
+/*
+ * ols_plan_set_tiling -- the forward kernel's tiling, for autotuners.  A
+ * workgroup transforms a tile of segments once and reuses the spectra for a
+ * run of filters (sec. 3.4: the segment is reused for every filter); work
+ * units of one tile and `filters_per_unit` filters are split into equal
+ * contiguous ranges over `workgroups_per_cu` x (compute units) persistent
+ * workgroups, so fewer workgroups give each more consecutive segments
+ * (segments per workgroup = number of segments / grid).
+ *   filters_per_unit   1 or 2 inverse transforms interleaved per unit
+ *                      (2 only for N <= 4096, and N <= 2048 for R2R);
+ *                      0 restores the library's choice
+ *   workgroups_per_cu  1 .. the kernel's occupancy; 0 = the occupancy
+ * The workgroup count leaves the output bit-identical; the filters-per-unit
+ * choice selects another kernel instance, whose results may differ in the
+ * last bits of float rounding.  Errors: INVALID_VALUE.
+ */
+ols_status_t ols_plan_set_tiling(ols_plan_t plan, int32_t filters_per_unit, int32_t workgroups_per_cu);
+
+/* Current tiling (see ols_plan_set_tiling) and the occupancy limit for it. */
+ols_status_t ols_plan_get_tiling(ols_plan_t plan, int32_t* filters_per_unit, int32_t* workgroups_per_cu,
+                                 int32_t* max_workgroups_per_cu);
+
 #ifdef __cplusplus
 }
 #endif

@@ -846,6 +846,44 @@ ols_status_t ols_plan_get_launch(ols_plan_t p, int32_t* grid, int32_t* block, in
   return OLS_SUCCESS;
 }
 
+static bool nf_allowed(const ols_plan_s* p, int nf) {
+  if (nf == 1) return true;
+  if (nf != 2) return false;
+  return (p->flags & OLS_REAL) ? p->N <= BATCH_NF2_MAX_N : p->N <= 4096;
+}
+
+ols_status_t ols_plan_set_tiling(ols_plan_t p, int32_t nf, int32_t wpc) {
+  try {
+    if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+    if (nf == 0) nf = (p->flags & OLS_REAL) ? choose_nf_real(p->N, p->K) : choose_nf(p->N, p->K);
+    if (!nf_allowed(p, nf)) return fail(OLS_ERROR_INVALID_VALUE, "filters_per_unit must be 1 or 2 (2 only for N <= 4096, R2R N <= 2048)");
+    int per_cu = 0;
+    hipError_t e = dispatch<RunOccupancy>(p->N, nf, p->flags, &per_cu);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    if (per_cu < 1) per_cu = 1;
+    if (wpc == 0) wpc = per_cu;
+    if (wpc < 1 || wpc > per_cu) return fail(OLS_ERROR_INVALID_VALUE, "workgroups_per_cu must be in [1, occupancy]");
+    p->nf = nf;
+    p->grid = wpc * p->cus;
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_plan_set_tiling");
+  }
+}
+
+ols_status_t ols_plan_get_tiling(ols_plan_t p, int32_t* nf, int32_t* wpc, int32_t* max_wpc) {
+  if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+  if (nf) *nf = p->nf;
+  if (wpc) *wpc = p->grid / p->cus;
+  if (max_wpc) {
+    int per_cu = 0;
+    hipError_t e = dispatch<RunOccupancy>(p->N, p->nf, p->flags, &per_cu);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    *max_wpc = per_cu < 1 ? 1 : per_cu;
+  }
+  return OLS_SUCCESS;
+}
+
 ols_status_t ols_plan_get_spectra(ols_plan_t p, void* out, ols_stream_t stream) {
   try {
     if (!p || !out) return fail(OLS_ERROR_INVALID_VALUE, "NULL argument");

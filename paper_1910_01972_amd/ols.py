@@ -82,6 +82,18 @@ class OLSPlan:
         check(lib().ols_plan_get_launch(self.handle, *[ctypes.byref(x) for x in v]), "ols_plan_get_launch")
         return dict(zip(("grid", "block", "cus"), (x.value for x in v)))
 
+    def set_tiling(self, filters_per_unit: int = 0, workgroups_per_cu: int = 0) -> None:
+        """Forward-kernel tiling (filters per work unit, persistent workgroups
+        per CU); 0 restores the library's choice.  Results change at most by
+        float rounding (filters per unit) or not at all (workgroups)."""
+        check(lib().ols_plan_set_tiling(self.handle, int(filters_per_unit), int(workgroups_per_cu)),
+              "ols_plan_set_tiling")
+
+    def tiling(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(3)]
+        check(lib().ols_plan_get_tiling(self.handle, *[ctypes.byref(x) for x in v]), "ols_plan_get_tiling")
+        return dict(zip(("filters_per_unit", "workgroups_per_cu", "max_workgroups_per_cu"), (x.value for x in v)))
+
     def set_hop(self, H: int) -> None:
         check(lib().ols_plan_set_hop(self.handle, int(H)), "ols_plan_set_hop")
 

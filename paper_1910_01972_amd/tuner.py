@@ -1,12 +1,16 @@
-"""Autotuner: the FFT (segment) length per (filter length M, filter count K).
+"""Autotuner: the FFT (segment) length and the kernel tiling per (filter
+length M, filter count K).
 
 The paper observes that each segment length is best for a band of filter
 lengths and that the best choice depends on the implementation (sec. 3.2,
 Fig. 9, sec. 5); the library's built-in choice is a cost model (FFT work per
 valid output).  This tuner measures instead: for every candidate N >= M it
-times the forward kernel on a synthetic signal and keeps the fastest per valid
-output sample.  Results are cached in a JSON file keyed by the GPU's
-architecture name, M and K.
+times the forward kernel on a synthetic signal and keeps the fastest; then,
+for that N, it times the tilings of the forward kernel -- filters per work
+unit (1 or 2 interleaved inverse transforms) and persistent workgroups per
+compute unit, which sets the number of consecutive segments each workgroup
+owns -- and keeps the fastest.  Results are cached in a JSON file keyed by the
+GPU's architecture name, M and K.
 
     python -m paper_1910_01972_amd.tuner --M 512 --K 8          # tune one cell
     python -m paper_1910_01972_amd.tuner --sweep                # the 12-cell sweep on 2^25 samples
@@ -54,9 +58,26 @@ def synthetic(Ns: int, K: int, M: int, seed: int):
     return torch.from_numpy(s).cuda(), torch.from_numpy(h).cuda()
 
 
+def tilings(plan) -> list:
+    """Candidate (filters per unit, workgroups per CU) for a plan."""
+    from ._lib import OLSError
+    out = []
+    for nf in (1, 2):
+        try:
+            plan.set_tiling(nf, 0)
+        except OLSError:
+            continue
+        for wpc in range(1, plan.tiling()["max_workgroups_per_cu"] + 1):
+            out.append((nf, wpc))
+    plan.set_tiling(0, 0)
+    return out
+
+
 def tune(M: int, K: int, Ns: int = 1 << 22, reps: int = 10, candidates=CANDIDATES, max_n: int = 8192,
-         data=None) -> dict:
-    """Time every candidate N >= M (N <= max_n); returns the fastest and all timings."""
+         data=None, tile: bool = True) -> dict:
+    """Time every candidate N >= M (N <= max_n) with the default tiling, then
+    every tiling at the fastest N; returns the best configuration and all
+    timings (ms per launch)."""
     from .ols import OLSPlan
     s, h = data if data is not None else synthetic(Ns, K, M, seed=M * 1000 + K)
     Ns = int(s.shape[0])
@@ -69,7 +90,25 @@ def tune(M: int, K: int, Ns: int = 1 << 22, reps: int = 10, candidates=CANDIDATE
         times[N] = _time_forward(plan, s, y, reps)
         plan.close()
     best = min(times, key=times.get)
-    return {"M": M, "K": K, "Ns": Ns, "N": best, "ms": times}
+    plan = OLSPlan(h, N=best)
+    default = plan.tiling()
+    cfg = (default["filters_per_unit"], default["workgroups_per_cu"])
+    tiling_ms = {f"{cfg[0]}x{cfg[1]}": times[best]}
+    if tile:
+        for nf, wpc in tilings(plan):
+            key = f"{nf}x{wpc}"
+            if key in tiling_ms:
+                continue
+            plan.set_tiling(nf, wpc)
+            tiling_ms[key] = _time_forward(plan, s, y, reps)
+        key = min(tiling_ms, key=tiling_ms.get)
+        cfg = tuple(int(v) for v in key.split("x"))
+    H = plan.info()["H"]
+    cus = plan.launch()["cus"]
+    plan.close()
+    nseg = -(-Ns // H)
+    return {"M": M, "K": K, "Ns": Ns, "N": best, "filters_per_unit": cfg[0], "workgroups_per_cu": cfg[1],
+            "segments_per_workgroup": nseg / (cfg[1] * cus), "ms": times, "tiling_ms": tiling_ms}
 
 
 class TuneCache:
@@ -83,14 +122,30 @@ class TuneCache:
     def key(self, M: int, K: int, max_n: int) -> str:
         return f"{_arch()}|M={M}|K={K}|max={max_n}"
 
-    def best(self, M: int, K: int, max_n: int = 8192, **kw) -> int:
+    def config(self, M: int, K: int, max_n: int = 8192, **kw) -> dict:
+        """Tuned {N, filters_per_unit, workgroups_per_cu} for (M, K), measured
+        once and cached."""
         k = self.key(M, K, max_n)
-        if k not in self.data:
-            self.data[k] = tune(M, K, max_n=max_n, **kw)["N"]
+        if not isinstance(self.data.get(k), dict):
+            r = tune(M, K, max_n=max_n, **kw)
+            self.data[k] = {"N": r["N"], "filters_per_unit": r["filters_per_unit"],
+                            "workgroups_per_cu": r["workgroups_per_cu"]}
             os.makedirs(os.path.dirname(self.path) or ".", exist_ok=True)
             with open(self.path, "w") as f:
                 json.dump(self.data, f, indent=1)
-        return int(self.data[k])
+        return dict(self.data[k])
+
+    def best(self, M: int, K: int, max_n: int = 8192, **kw) -> int:
+        return int(self.config(M, K, max_n=max_n, **kw)["N"])
+
+    def plan(self, h: torch.Tensor, **kw):
+        """An OLSPlan for the filter bank h with the tuned N and tiling."""
+        from .ols import OLSPlan
+        K, M = int(h.shape[0]), int(h.shape[1])
+        c = self.config(M, K, **kw)
+        p = OLSPlan(h, N=c["N"])
+        p.set_tiling(c["filters_per_unit"], c["workgroups_per_cu"])
+        return p
 
     def batched_fft_length(self, M: int, K: int) -> int:
         """Chooser for OLSBatch (batched items use N <= 4096)."""
@@ -110,13 +165,17 @@ def sweep(reps: int = 10, tune_ns: int = 1 << 22):
         s, h = synthetic(wl.Ns, wl.K, wl.M, seed=wl.seed)
         y = torch.empty((wl.K, wl.Ns), dtype=torch.complex64, device="cuda")
         plan = OLSPlan(h, N=t["N"])
+        ms_default = _time_forward(plan, s, y, reps)
+        plan.set_tiling(t["filters_per_unit"], t["workgroups_per_cu"])
         ms = _time_forward(plan, s, y, reps)
         auto = OLSPlan(h, N=0)
         auto_n = auto.info()["N"]
         auto.close()
         alg = 8.0 * wl.K * wl.Ns + 8.0 * wl.Ns + 8.0 * wl.K * wl.M
         rec = {"cell": wl.name, "M": wl.M, "K": wl.K, "Ns": wl.Ns, "tuned_N": t["N"], "cost_model_N": auto_n,
-               "proxy_ms": t["ms"], "ms": ms, "samples_per_s": wl.K * wl.Ns / (ms * 1e-3),
+               "filters_per_unit": t["filters_per_unit"], "workgroups_per_cu": t["workgroups_per_cu"],
+               "proxy_ms": t["ms"], "proxy_tiling_ms": t["tiling_ms"], "ms_default_tiling": ms_default,
+               "ms": ms, "samples_per_s": wl.K * wl.Ns / (ms * 1e-3),
                "GBps": alg / (ms * 1e-3) / 1e9, "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         plan.close()
         del s, h, y
