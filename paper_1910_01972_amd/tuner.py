@@ -83,9 +83,11 @@ def tune(M: int, K: int, Ns: int = 1 << 22, reps: int = 10, candidates=CANDIDATE
     Ns = int(s.shape[0])
     y = torch.empty((K, Ns), dtype=torch.complex64, device="cuda")
     times = {}
-    for N in candidates:
-        if N < M or N > max_n:
-            continue
+    usable = [N for N in candidates if M <= N <= max_n]
+    # a segment keeps N - (M - 1) outputs; below a quarter of N the overlap
+    # dominates and the candidate cannot win (at N = M it keeps one sample)
+    good = [N for N in usable if 4 * (N - M + 1) >= N]
+    for N in good or usable:
         plan = OLSPlan(h, N=N)
         times[N] = _time_forward(plan, s, y, reps)
         plan.close()
@@ -165,15 +167,21 @@ def sweep(reps: int = 10, tune_ns: int = 1 << 22):
         s, h = synthetic(wl.Ns, wl.K, wl.M, seed=wl.seed)
         y = torch.empty((wl.K, wl.Ns), dtype=torch.complex64, device="cuda")
         plan = OLSPlan(h, N=t["N"])
-        ms_default = _time_forward(plan, s, y, reps)
-        plan.set_tiling(t["filters_per_unit"], t["workgroups_per_cu"])
-        ms = _time_forward(plan, s, y, reps)
+        # default and tuned tiling timed alternately (twice each, after a
+        # longer warm-up), the lower median of each kept
+        ms_default, ms = float("inf"), float("inf")
+        for _ in range(2):
+            plan.set_tiling(0, 0)
+            ms_default = min(ms_default, _time_forward(plan, s, y, max(reps, 20), warmup=20))
+            plan.set_tiling(t["filters_per_unit"], t["workgroups_per_cu"])
+            ms = min(ms, _time_forward(plan, s, y, max(reps, 20), warmup=20))
         auto = OLSPlan(h, N=0)
         auto_n = auto.info()["N"]
         auto.close()
         alg = 8.0 * wl.K * wl.Ns + 8.0 * wl.Ns + 8.0 * wl.K * wl.M
         rec = {"cell": wl.name, "M": wl.M, "K": wl.K, "Ns": wl.Ns, "tuned_N": t["N"], "cost_model_N": auto_n,
                "filters_per_unit": t["filters_per_unit"], "workgroups_per_cu": t["workgroups_per_cu"],
+               "segments_per_workgroup": -(-wl.Ns // plan.info()["H"]) / plan.launch()["grid"],
                "proxy_ms": t["ms"], "proxy_tiling_ms": t["tiling_ms"], "ms_default_tiling": ms_default,
                "ms": ms, "samples_per_s": wl.K * wl.Ns / (ms * 1e-3),
                "GBps": alg / (ms * 1e-3) / 1e9, "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
