@@ -145,8 +145,16 @@ class OLSPlan:
             raise ValueError("gy must have shape (K, N_s)")
         if need_ds and ds is None:
             ds = torch.empty(Ns, dtype=torch.complex64, device=s.device)
+        elif need_ds:
+            _check_c64(ds, "ds", 1)
+            if int(ds.shape[0]) != Ns:
+                raise ValueError("ds must have shape (N_s,)")
         if need_dh and dh is None:
             dh = torch.empty((self.K, self.M), dtype=torch.complex64, device=s.device)
+        elif need_dh:
+            _check_c64(dh, "dh", 2)
+            if tuple(dh.shape) != (self.K, self.M):
+                raise ValueError("dh must have shape (K, M)")
         p_ds = ctypes.c_void_p(ds.data_ptr()) if need_ds else ctypes.c_void_p()
         p_dh = ctypes.c_void_p(dh.data_ptr()) if need_dh else ctypes.c_void_p()
         check(lib().ols_backward(self.handle, ctypes.c_void_p(s.data_ptr()), Ns, ctypes.c_void_p(gy.data_ptr()),
