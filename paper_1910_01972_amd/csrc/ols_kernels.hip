@@ -27,6 +27,22 @@ namespace ols {
 // ---------------------------------------------------------------------------
 // Transform drivers (device): passes in registers, exchanges through LDS.
 // ---------------------------------------------------------------------------
+// Synchronisation of an exchange.  When a transform spans several waves
+// (G > 64) the exchange crosses waves and needs a workgroup barrier.  When
+// every transform lives inside one wave (G <= 64), a wave only ever touches
+// the LDS interval of its own transforms, in every exchange and every buffer,
+// and the LDS completes a wave's operations in program order: no barrier is
+// needed, only a fence that keeps the compiler from reordering the reads of
+// other lanes' data before the writes.
+template <int N>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (Geo<N>::G <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Exchanges alternate between two LDS buffers of Geo<N>::LDS elements.  All
 // lanes of the workgroup see the same sequence of exchanges, so one barrier
 // per exchange suffices: a lane that passes the barrier of exchange n+1 knows
@@ -37,7 +53,7 @@ __device__ __forceinline__ void exchange(float2 (&x)[16], float2* lds, int& par,
   float2* buf = lds + (par ? Geo<N>::LDS : 0);
   par ^= 1;
   lds_store<N, E, KW>(buf, x, grp, g);
-  __syncthreads();
+  exchange_sync<N>();
   lds_load<N, E, KR>(buf, x, grp, g);
 }
 
@@ -51,10 +67,10 @@ __device__ __forceinline__ void exchange_nf(float2 (&x)[NF][16], float2* lds, in
   } else {
 #pragma unroll
     for (int f = 0; f < NF; ++f) lds_store<N, E, KW>(lds + f * Geo<N>::LDS, x[f], grp, g);
-    __syncthreads();
+    exchange_sync<N>();
 #pragma unroll
     for (int f = 0; f < NF; ++f) lds_load<N, E, KR>(lds + f * Geo<N>::LDS, x[f], grp, g);
-    __syncthreads();
+    exchange_sync<N>();
   }
 }
 
@@ -305,6 +321,10 @@ __global__ __launch_bounds__(256) void ols_batched_kernel(const BatchItem* __res
     const int64_t end = it.unit_begin + it.units;
     if (end <= u) continue;  // items without units
     const int64_t a = u - it.unit_begin, b = (u1 < end ? u1 : end) - it.unit_begin;
+    // items of different N lay out the LDS buffers differently, and
+    // single-wave transforms exchange without barriers: every wave must have
+    // finished with the previous item's buffers
+    __syncthreads();
     switch (it.N) {
       case 256: batched_item<256>(it, tw256, a, b, lds, par); break;
       case 512: batched_item<512>(it, tw512, a, b, lds, par); break;
