@@ -48,9 +48,11 @@ __device__ __forceinline__ void exchange_sync() {
 // per exchange suffices: a lane that passes the barrier of exchange n+1 knows
 // every lane has finished reading exchange n (program order), and exchange n+2
 // reuses exchange n's buffer.  `par` selects the buffer of the next exchange.
+// Single-wave transforms need no second buffer (their exchanges are
+// wave-private and in order), so they keep using the first.
 template <int N, int E, int KW, int KR>
 __device__ __forceinline__ void exchange(float2 (&x)[16], float2* lds, int& par, int grp, int g) {
-  float2* buf = lds + (par ? Geo<N>::LDS : 0);
+  float2* buf = lds + ((Geo<N>::G > 64 && par) ? Geo<N>::LDS : 0);
   par ^= 1;
   lds_store<N, E, KW>(buf, x, grp, g);
   exchange_sync<N>();
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const void* __r
                                                                  int K, int D, int H, int64_t ntiles,
                                                                  const float2* __restrict__ twt) {
   using GE = Geo<N>;
-  constexpr int BUFS = NF == 1 ? 2 : NF;
+  constexpr int BUFS = (NF == 1 && GE::G > 64) ? 2 : NF;  // double-buffered only across waves
   __shared__ float2 lds[BUFS * GE::LDS];
   const int64_t U = ntiles * ((K + NF - 1) / NF);
   const int64_t u0 = first_unit(U, gridDim.x, blockIdx.x);

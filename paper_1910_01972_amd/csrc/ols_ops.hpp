@@ -301,12 +301,16 @@ OLS_HD void store_valid_pair(const float2 (&x)[16], float* __restrict__ yrow, in
   }
 }
 
-// Filters per work unit of the forward kernels: two interleaved transforms when
-// registers allow it (N <= 4096) and the filter count wastes little on a
-// padded last group; the batched kernel allows two only up to N = 2048.
+// Filters per work unit of the forward kernels: two interleaved transforms
+// when a transform spans several waves (N = 2048, 4096: the pair shares each
+// exchange's barriers), registers allow it and the filter count wastes little
+// on a padded last group.  Single-wave transforms (N <= 1024) exchange
+// without barriers and measured as fast or faster with one filter per unit.
 constexpr int BATCH_NF2_MAX_N = 2048;
-OLS_HD int choose_nf(int N, int K) { return (N <= 4096 && (K % 2 == 0 || K >= 9)) ? 2 : 1; }
-OLS_HD int choose_nf_batched(int N, int K) { return N <= BATCH_NF2_MAX_N ? choose_nf(N, K) : 1; }
+OLS_HD int choose_nf(int N, int K) { return (N >= 2048 && N <= 4096 && (K % 2 == 0 || K >= 9)) ? 2 : 1; }
+// The batched kernel's registers are set by its largest branch, so one filter
+// per unit saves nothing there and two measured faster at every N <= 2048.
+OLS_HD int choose_nf_batched(int N, int K) { return (N <= BATCH_NF2_MAX_N && (K % 2 == 0 || K >= 9)) ? 2 : 1; }
 // R2R (segment pairs) needs a few more registers per transform: two filters
 // per unit only up to N = 2048 as well.
 OLS_HD int choose_nf_real(int N, int K) { return N <= BATCH_NF2_MAX_N ? choose_nf(N, K) : 1; }
