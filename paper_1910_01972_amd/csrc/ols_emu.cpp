@@ -484,6 +484,35 @@ struct RunLds {
     return 0;
   }
 };
+// Exchange E is wave-local when every LDS cell is read (pass E+1 layout) by a
+// lane of the same wave that wrote it (pass E layout); out[E] = 1 or 0.
+template <int N, int E>
+void wave_locality(int32_t* out) {
+  using GE = Geo<N>;
+  std::map<int, int> writer;
+  for (int j = 0; j < GE::slots(E); ++j)
+    for (int a = 0; a < GE::radix(E); ++a)
+      for (int t = 0; t < GE::WG; ++t)
+        writer[lds_base<N, E, E>(t / GE::G, t % GE::G) + lds_off<N, E, E>(j, a)] = t / 64;
+  int local = 1;
+  for (int j = 0; j < GE::slots(E + 1); ++j)
+    for (int a = 0; a < GE::radix(E + 1); ++a)
+      for (int t = 0; t < GE::WG; ++t) {
+        auto it = writer.find(lds_base<N, E, E + 1>(t / GE::G, t % GE::G) + lds_off<N, E, E + 1>(j, a));
+        if (it == writer.end() || it->second != t / 64) local = 0;
+      }
+  out[E] = local;
+  if constexpr (E + 1 < GE::P - 1) wave_locality<N, E + 1>(out);
+}
+
+template <int N>
+struct RunWaveLocal {
+  static int run(int32_t* out) {
+    wave_locality<N, 0>(out);
+    return 0;
+  }
+};
+
 template <int N>
 struct RunGeo {
   static int run(int32_t* out) {
@@ -589,5 +618,9 @@ int ols_emu_lds_report(int N, int64_t* out) { return ols::emu::dispatch<ols::emu
 
 // out[0..6] = G, P, R0, WG, SEGS, LDS (float2), TWR
 int ols_emu_geometry(int N, int32_t* out) { return ols::emu::dispatch<ols::emu::RunGeo>(N, out); }
+
+// out[E] = 1 if exchange E (between passes E and E+1) keeps every value in
+// the wave that wrote it, for E = 0 .. P-2.
+int ols_emu_wave_local(int N, int32_t* out) { return ols::emu::dispatch<ols::emu::RunWaveLocal>(N, out); }
 
 }  // extern "C"

@@ -61,7 +61,12 @@ __device__ __forceinline__ void exchange(float2 (&x)[16], float2* lds, int& par,
 
 // NF independent transforms exchanged together: one buffer each, written
 // before one barrier and read after it; the second barrier protects the
-// buffers from the next exchange's writes.
+// buffers from the next exchange's writes.  The last exchange of the
+// transform (between passes P-2 and P-1) keeps every value inside the wave
+// that wrote it (both layouts put position bits 10 and up in the wave index;
+// the host emulator checks this for every N), so its first barrier is
+// replaced by a wave-scope fence; the second still guards the next exchange,
+// whose writes cross waves.
 template <int N, int NF, int E, int KW, int KR>
 __device__ __forceinline__ void exchange_nf(float2 (&x)[NF][16], float2* lds, int& par, int grp, int g) {
   if constexpr (NF == 1) {
@@ -69,7 +74,8 @@ __device__ __forceinline__ void exchange_nf(float2 (&x)[NF][16], float2* lds, in
   } else {
 #pragma unroll
     for (int f = 0; f < NF; ++f) lds_store<N, E, KW>(lds + f * Geo<N>::LDS, x[f], grp, g);
-    exchange_sync<N>();
+    if constexpr (E == Geo<N>::P - 2) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    else exchange_sync<N>();
 #pragma unroll
     for (int f = 0; f < NF; ++f) lds_load<N, E, KR>(lds + f * Geo<N>::LDS, x[f], grp, g);
     exchange_sync<N>();

@@ -27,6 +27,8 @@ def emu() -> ctypes.CDLL:
         L.ols_emu_spectra.argtypes = [I32, P, I32, I32, P]
         L.ols_emu_lds_report.argtypes = [I32, P]
         L.ols_emu_geometry.argtypes = [I32, P]
+        L.ols_emu_wave_local.argtypes = [I32, P]
+        L.ols_emu_wave_local.restype = I32
         L.ols_emu_backward.argtypes = [I32, P, I64, P, P, I32, I32, I32, I32, I32, P, P]
         L.ols_emu_backward.restype = I32
         for f in (L.ols_emu_forward, L.ols_emu_spectra, L.ols_emu_lds_report, L.ols_emu_geometry):
@@ -44,6 +46,15 @@ def geometry(N: int) -> dict:
     if emu().ols_emu_geometry(N, _ptr(out)) != 0:
         raise ValueError(N)
     return dict(zip(("G", "P", "R0", "WG", "SEGS", "LDS", "TWR"), out.tolist()))
+
+
+def wave_local(N: int) -> list:
+    """Per exchange E = 0 .. P-2: True if every value stays in the wave that
+    wrote it."""
+    out = np.zeros(8, dtype=np.int32)
+    if emu().ols_emu_wave_local(N, _ptr(out)) != 0:
+        raise ValueError(N)
+    return [bool(v) for v in out[:geometry(N)["P"] - 1]]
 
 
 def lds_report(N: int) -> dict:

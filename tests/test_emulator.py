@@ -230,3 +230,16 @@ def test_real_to_real_hop_invariance():
         assert D >= 99
         y, ok = emu.forward_post(s, h, N, D, H, grid=5, post=4)
         assert ok and np.all(_rel(y, ref) <= 1e-5), (N, H)
+
+
+@pytest.mark.parametrize("N", NS)
+def test_last_exchange_is_wave_local(N):
+    """The kernels drop the first barrier of the transform's last exchange
+    (passes P-2 <-> P-1) because every value stays in the wave that wrote it;
+    single-wave transforms (N <= 1024) need no barrier in any exchange."""
+    local = emu.wave_local(N)
+    assert local[-1], local
+    if emu.geometry(N)["G"] <= 64:
+        assert all(local), local
+    else:
+        assert not local[0], local  # the first exchange crosses waves: it keeps its barriers
