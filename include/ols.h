@@ -129,6 +129,10 @@ ols_status_t ols_plan_set_hop(ols_plan_t plan, int32_t H);
  * D >= M - 1), K and M.  Any output pointer may be NULL. */
 ols_status_t ols_plan_get_info(ols_plan_t plan, int32_t* N, int32_t* H, int32_t* D, int32_t* K, int32_t* M);
 
+/* The plan's FFT (segment) length N (sec. 3.2), the library's or the caller's
+ * choice.  Errors: INVALID_VALUE (NULL plan or N). */
+ols_status_t ols_plan_get_fft_length(ols_plan_t plan, int32_t* N);
+
 /*
  * ols_plan_get_spectra -- copy the plan's filter spectra, in natural frequency
  * order, to `out` (device, complex64 [K][N]): out[r][m] = (1/N) *
@@ -225,6 +229,12 @@ typedef struct {
 } ols_batch_item_t;
 
 ols_status_t ols_batch_plan(ols_batch_t* batch, const ols_batch_item_t* items, int32_t n, ols_stream_t stream);
+
+/* Device bytes that ols_batch_plan allocates for these items (filter spectra
+ * K x N complex64 per item at the FFT length it would choose, the item table
+ * and the twiddle tables), without allocating anything; items are validated
+ * as by ols_batch_plan.  Errors: as ols_batch_plan (host checks only). */
+ols_status_t ols_batched_workspace_size(const ols_batch_item_t* items, int32_t n, size_t* bytes);
 
 /* One persistent launch over all items of the batch, on `stream`.
  * Allocates nothing; capturable.  Errors: INVALID_VALUE, HIP. */

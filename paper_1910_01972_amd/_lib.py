@@ -39,6 +39,8 @@ SIGNATURES = {
     "ols_plan_get_spectra": (_I32, [_P, _P, _P]),
     "ols_plan_get_launch": (_I32, [_P, _PI32, _PI32, _PI32]),
     "ols_plan_set_tiling": (_I32, [_P, _I32, _I32]),
+    "ols_plan_get_fft_length": (_I32, [_P, _PI32]),
+    "ols_batched_workspace_size": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_size_t)]),
     "ols_plan_get_tiling": (_I32, [_P, _PI32, _PI32, _PI32]),
     "ols_forward": (_I32, [_P, _P, _I64, _P, _P]),
     "ols_plan_destroy": (_I32, [_P]),

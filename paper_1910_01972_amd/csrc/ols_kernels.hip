@@ -866,6 +866,12 @@ ols_status_t ols_plan_get_info(ols_plan_t p, int32_t* N, int32_t* H, int32_t* D,
   return OLS_SUCCESS;
 }
 
+ols_status_t ols_plan_get_fft_length(ols_plan_t p, int32_t* N) {
+  if (!p || !N) return fail(OLS_ERROR_INVALID_VALUE, "NULL argument");
+  *N = p->N;
+  return OLS_SUCCESS;
+}
+
 ols_status_t ols_plan_get_launch(ols_plan_t p, int32_t* grid, int32_t* block, int32_t* cus) {
   if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
   if (grid) *grid = p->grid;
@@ -1021,6 +1027,57 @@ ols_status_t ols_plan_destroy(ols_plan_t p) {
   return OLS_SUCCESS;
 }
 
+// Validates batch item i and resolves its FFT length (the caller's, or the
+// cost model's when it is 0).
+static ols_status_t batch_item_fft_length(const ols_batch_item_t& it, int i, int* N_out) {
+  const std::string where = "item " + std::to_string(i) + ": ";
+  if (it.K < 1 || it.M < 1 || it.N_s < 0) return fail(OLS_ERROR_INVALID_VALUE, where + "K, M >= 1 and N_s >= 0 required");
+  if (!it.h || (it.N_s > 0 && (!it.s || !it.y))) return fail(OLS_ERROR_INVALID_VALUE, where + "NULL pointer");
+  if (((uintptr_t)it.s | (uintptr_t)it.y | (uintptr_t)it.h) % 8) return fail(OLS_ERROR_INVALID_VALUE, where + "pointers must be 8-byte aligned");
+  if (it.N_s > ((int64_t)1 << 56) / 8 / it.K) return fail(OLS_ERROR_INVALID_VALUE, where + "K*N_s*8 overflows");
+  if (it.N_s > 0 && ranges_overlap(it.s, (size_t)it.N_s * 8, it.y, (size_t)it.N_s * 8 * it.K))
+    return fail(OLS_ERROR_INVALID_VALUE, where + "y overlaps s");
+  int N = it.N;
+  if (N == 0) {
+    double best = 1e301;
+    for (int c = OLS_MIN_FFT_LENGTH; c <= OLS_MAX_BATCH_FFT_LENGTH; c *= 2) {
+      if (c < it.M) continue;
+      const double cost = cost_per_output(c, it.M, it.K);
+      if (cost < best) { best = cost; N = c; }
+    }
+    if (N == 0) return fail(OLS_ERROR_UNSUPPORTED, where + "filter longer than the largest batched FFT length");
+  }
+  if (!is_pow2(N) || N < OLS_MIN_FFT_LENGTH || N > OLS_MAX_BATCH_FFT_LENGTH)
+    return fail(OLS_ERROR_UNSUPPORTED, where + "batched N must be a power of two in [256, 4096]");
+  if (it.M > N) return fail(OLS_ERROR_INVALID_VALUE, where + "M must be <= N");
+  *N_out = N;
+  return OLS_SUCCESS;
+}
+
+static size_t batch_twiddle_elems() {
+  return RunTwiddles<256>::run().size() + RunTwiddles<512>::run().size() + RunTwiddles<1024>::run().size() +
+         RunTwiddles<2048>::run().size() + RunTwiddles<4096>::run().size();
+}
+
+ols_status_t ols_batched_workspace_size(const ols_batch_item_t* items, int32_t n, size_t* bytes) {
+  try {
+    if (!bytes) return fail(OLS_ERROR_INVALID_VALUE, "bytes is NULL");
+    *bytes = 0;
+    if (!items || n < 1) return fail(OLS_ERROR_INVALID_VALUE, "items is NULL or n < 1");
+    size_t spec = 0;
+    for (int i = 0; i < n; ++i) {
+      int N = 0;
+      const ols_status_t r = batch_item_fft_length(items[i], i, &N);
+      if (r != OLS_SUCCESS) return r;
+      spec += (size_t)items[i].K * N;
+    }
+    *bytes = (spec + batch_twiddle_elems()) * sizeof(float2) + (size_t)n * sizeof(BatchItem);
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_batched_workspace_size");
+  }
+}
+
 ols_status_t ols_batch_plan(ols_batch_t* out, const ols_batch_item_t* items, int32_t n, ols_stream_t stream) {
   try {
     if (!out) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL");
@@ -1034,24 +1091,9 @@ ols_status_t ols_batch_plan(ols_batch_t* out, const ols_batch_item_t* items, int
     int64_t units = 0;
     for (int i = 0; i < n; ++i) {
       const ols_batch_item_t& it = items[i];
-      const std::string where = "item " + std::to_string(i) + ": ";
-      if (it.K < 1 || it.M < 1 || it.N_s < 0) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "K, M >= 1 and N_s >= 0 required"); }
-      if (!it.h || (it.N_s > 0 && (!it.s || !it.y))) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "NULL pointer"); }
-      if (((uintptr_t)it.s | (uintptr_t)it.y | (uintptr_t)it.h) % 8) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "pointers must be 8-byte aligned"); }
-      if (it.N_s > ((int64_t)1 << 56) / 8 / it.K) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "K*N_s*8 overflows"); }
-      if (it.N_s > 0 && ranges_overlap(it.s, (size_t)it.N_s * 8, it.y, (size_t)it.N_s * 8 * it.K)) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "y overlaps s"); }
-      int N = it.N;
-      if (N == 0) {
-        double best = 1e301;
-        for (int c = OLS_MIN_FFT_LENGTH; c <= OLS_MAX_BATCH_FFT_LENGTH; c *= 2) {
-          if (c < it.M) continue;
-          const double cost = cost_per_output(c, it.M, it.K);
-          if (cost < best) { best = cost; N = c; }
-        }
-        if (N == 0) { destroy_batch(b); return fail(OLS_ERROR_UNSUPPORTED, where + "filter longer than the largest batched FFT length"); }
-      }
-      if (!is_pow2(N) || N < OLS_MIN_FFT_LENGTH || N > OLS_MAX_BATCH_FFT_LENGTH) { destroy_batch(b); return fail(OLS_ERROR_UNSUPPORTED, where + "batched N must be a power of two in [256, 4096]"); }
-      if (it.M > N) { destroy_batch(b); return fail(OLS_ERROR_INVALID_VALUE, where + "M must be <= N"); }
+      int N = 0;
+      const ols_status_t r = batch_item_fft_length(it, i, &N);
+      if (r != OLS_SUCCESS) { destroy_batch(b); return r; }
       BatchItem& d = b->items_host[i];
       d.s = (const float2*)it.s;
       d.y = (float2*)it.y;

@@ -89,6 +89,11 @@ class OLSPlan:
         check(lib().ols_plan_set_tiling(self.handle, int(filters_per_unit), int(workgroups_per_cu)),
               "ols_plan_set_tiling")
 
+    def fft_length(self) -> int:
+        N = ctypes.c_int32()
+        check(lib().ols_plan_get_fft_length(self.handle, ctypes.byref(N)), "ols_plan_get_fft_length")
+        return N.value
+
     def tiling(self) -> dict:
         v = [ctypes.c_int32() for _ in range(3)]
         check(lib().ols_plan_get_tiling(self.handle, *[ctypes.byref(x) for x in v]), "ols_plan_get_tiling")
@@ -230,6 +235,9 @@ class OLSBatch:
             self.inputs.append((s, h))
             self.outputs.append(y)
             arr[i] = BatchItem(s.data_ptr(), int(s.shape[0]), h.data_ptr(), K, M, N, y.data_ptr())
+        nbytes = ctypes.c_size_t()
+        check(lib().ols_batched_workspace_size(arr, n, ctypes.byref(nbytes)), "ols_batched_workspace_size")
+        self.workspace_bytes = int(nbytes.value)
         self._handle = ctypes.c_void_p()
         check(lib().ols_batch_plan(ctypes.byref(self._handle), arr, n, _stream_handle(stream)), "ols_batch_plan")
         self.n = n

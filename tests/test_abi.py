@@ -81,3 +81,30 @@ def test_misaligned_filter_pointer_rejected():
     buf = ctypes.create_string_buffer(64)
     st, _ = _plan(ctypes.c_void_p(ctypes.addressof(buf) + 4), 1, 4, 256)
     assert st == 1
+
+
+def test_batched_workspace_size_host_only():
+    """ols_batched_workspace_size validates items and sizes the batch on the
+    host alone (fake, never dereferenced pointers; no GPU call)."""
+    L = _lib.lib()
+    BI = _lib.BatchItem
+
+    def size(items):
+        arr = (BI * len(items))(*items)
+        out = ctypes.c_size_t()
+        rc = L.ols_batched_workspace_size(arr, len(items), ctypes.byref(out))
+        return rc, out.value
+
+    base = 1 << 40
+    a = BI(base, 1000, base + (1 << 30), 3, 100, 512, base + (2 << 30))
+    b = BI(base + (3 << 30), 5000, base + (4 << 30), 2, 30, 256, base + (5 << 30))
+    rc, n512 = size([a, b])
+    assert rc == 0 and n512 > 0
+    a256 = BI(base, 1000, base + (1 << 30), 3, 100, 256, base + (2 << 30))
+    rc, n256 = size([a256, b])
+    assert rc == 0 and n512 - n256 == 3 * (512 - 256) * 8  # spectra K x N complex64
+    bad = BI(base, 1000, base + (1 << 30), 3, 100, 8192, base + (2 << 30))   # batched N <= 4096
+    assert size([bad])[0] == 2
+    overlap = BI(base, 1000, base + (1 << 30), 3, 100, 512, base + 8)          # y overlaps s
+    assert size([overlap])[0] == 1
+    assert L.ols_batched_workspace_size(None, 1, None) == 1
