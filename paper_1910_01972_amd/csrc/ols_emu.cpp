@@ -355,7 +355,7 @@ struct EmuItem {
   const float2* s;
   float2* y;
   std::vector<float2> F;
-  int64_t Ns, unit_begin, units;
+  int64_t Ns, unit_begin, units, tile_begin = 0, ntiles = 0;
   int K, M, N, D, H, nf;
 };
 
@@ -563,7 +563,7 @@ int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t
                     const int* K, const int* M, const int* N, const int* D, const int* H, int grid) {
   using namespace ols::emu;
   std::vector<EmuItem> items(n);
-  int64_t units = 0;
+  int64_t units = 0, tiles = 0;
   for (int i = 0; i < n; ++i) {
     EmuItem& it = items[i];
     it.s = (const float2*)s[i];
@@ -577,30 +577,28 @@ int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t
     it.nf = ols::choose_nf_batched(it.N, it.K);
     const int segs = 4096 / it.N;
     const int64_t nseg = (it.Ns + it.H - 1) / it.H;
+    it.ntiles = (nseg + segs - 1) / segs;
     it.unit_begin = units;
-    it.units = ((nseg + segs - 1) / segs) * ((it.K + it.nf - 1) / it.nf);
+    it.units = it.ntiles * ((it.K + it.nf - 1) / it.nf);
     units += it.units;
+    it.tile_begin = tiles;
+    tiles += it.ntiles;
     if (dispatch<SpecN>(it.N, &it, (const float2*)h[i]) != 0) return 2;
   }
-  const int64_t P = units < grid ? units : grid;
+  // the device schedule: tiles of all items dealt round-robin to the grid
+  const int64_t P = tiles < grid ? tiles : grid;
   for (int64_t b = 0; b < P; ++b) {
-    const int64_t u0 = ols::first_unit(units, P, b), u1 = ols::first_unit(units, P, b + 1);
-    if (u0 >= u1) continue;
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) / 2;
-      if (items[mid].unit_begin <= u0) lo = mid; else hi = mid - 1;
-    }
-    int64_t u = u0;
-    for (int i = lo; i < n && u < u1; ++i) {
+    int i = 0;
+    for (int64_t t = b; t < tiles; t += P) {
+      while (i + 1 < n && items[i + 1].tile_begin <= t) ++i;
       EmuItem& it = items[i];
-      const int64_t end = it.unit_begin + it.units;
-      if (end <= u) continue;
-      const int64_t a = u - it.unit_begin, e = (u1 < end ? u1 : end) - it.unit_begin;
-      if (dispatch<RangeN>(it.N, &it, a, e) != 0) return 3;
-      u = it.unit_begin + e;
+      if (t < it.tile_begin || t >= it.tile_begin + it.ntiles) return 4;  // walk invariant
+      const int64_t per_tile = it.units / it.ntiles;
+      const int64_t a = (t - it.tile_begin) * per_tile;
+      if (dispatch<RangeN>(it.N, &it, a, a + per_tile) != 0) return 3;
     }
   }
+  (void)units;
   return 0;
 }
 
