@@ -137,7 +137,9 @@ ols_status_t ols_plan_get_fft_length(ols_plan_t plan, int32_t* N);
  * ols_plan_get_spectra -- copy the plan's filter spectra, in natural frequency
  * order, to `out` (device, complex64 [K][N]): out[r][m] = (1/N) *
  * sum_{n<M} h_r[n] exp(-2 pi i m n / N) (the forward FFT of the zero-padded
- * filter, eq. 2, with the inverse transform's 1/N folded in).  Internally the
+ * filter, eq. 2, with the inverse transform's 1/N folded in; for a plan with
+ * OLS_POST_DERIVATIVE the filter is h_r[n] - h_r[n-1], n <= M, as applied;
+ * for OLS_REAL the real filter's complex spectrum).  Internally the
  * spectra are kept in the transform's digit-reversed order (sec. 3.4); this
  * call undoes the permutation.  Enqueued on `stream`.  Errors: INVALID_VALUE, HIP.
  */

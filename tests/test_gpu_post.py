@@ -137,3 +137,24 @@ def test_post_full_size_sampled(ols):
             ref = post.power(conv.direct_conv_at(s, h, idx))
         assert np.all(rel_rows(got, ref) <= TOL), rel_rows(got, ref)
         plan.close()
+
+
+def test_spectra_of_derivative_and_real_plans(ols):
+    """The plan's spectra are those of the filters as applied: h[n] - h[n-1]
+    (n <= M) for the derivative, the real filter's spectrum for R2R."""
+    N, K, M = 512, 3, 60
+    _, h = workloads.make_signal_filters(1, K, M, seed=77)
+    plan = ols.OLSPlan(dev(h), N=N, derivative=True)
+    got = plan.spectra().cpu().numpy()
+    hd = np.zeros((K, N), dtype=np.complex128)
+    hd[:, :M] += h
+    hd[:, 1:M + 1] -= h
+    want = conv.fft(hd) / N
+    assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
+    plan.close()
+    _, hr = workloads.make_real_signal_filters(1, K, M, seed=78)
+    plan = ols.OLSPlan(dev(hr), N=N)
+    got = plan.spectra().cpu().numpy()
+    want = conv.fft(np.concatenate([hr.astype(np.float64), np.zeros((K, N - M))], axis=1)) / N
+    assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
+    plan.close()
