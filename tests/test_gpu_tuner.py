@@ -103,3 +103,26 @@ def test_tuner_choice_cached_and_applied(ols, tmp_path):
     assert np.all(np.linalg.norm(got - want, axis=1) <= 1e-5 * np.linalg.norm(want, axis=1))
     plan.close()
     sys.stdout.flush()
+
+
+def test_batched_with_tuned_fft_lengths(ols, tmp_path):
+    """OLSBatch with the tuner choosing each item's N (cached per (M, K)):
+    every item uses the cached choice and matches the oracle."""
+    from paper_1910_01972_amd import tuner
+    cache = tuner.TuneCache(str(tmp_path / "tune.json"))
+    shapes = [(20000, 3, 40), (9000, 2, 300), (20000, 3, 40)]
+    items, host = [], []
+    for i, (Ns, K, M) in enumerate(shapes):
+        s, h = workloads.make_signal_filters(Ns, K, M, seed=90 + i)
+        items.append((dev(s), dev(h)))
+        host.append((s, h))
+    b = ols.OLSBatch(items, fft_length=cache.batched_fft_length)
+    outs = b.run()
+    torch.cuda.synchronize()
+    for i, ((s, h), y) in enumerate(zip(host, outs)):
+        K, M = h.shape
+        assert b.item(i)["N"] == cache.best(M, K, max_n=4096) <= 4096
+        want = conv.direct_conv(s, h)
+        assert np.all(np.linalg.norm(y.cpu().numpy() - want, axis=1) <= 1e-5 * np.linalg.norm(want, axis=1))
+    assert len(json.load(open(str(tmp_path / "tune.json")))) == 2  # one entry per distinct (M, K)
+    b.close()
