@@ -125,6 +125,10 @@ SMALL = [
     (50000, 9, 100, 1024, None),      # odd K >= 9: two filters per unit, ragged last group
     (20001, 11, 300, 4096, 1000),
     (33333, 6, 1, 256, None),         # even K, N = 256 (16 transforms per workgroup)
+    (40000, 3, 500, 2048, None),      # odd K < 9 at N = 2048: one filter per unit, double-buffered LDS
+    (40000, 7, 500, 4096, 2000),      # odd K < 9 at N = 4096
+    (262147, 64, 32, 256, None),      # many filters on single-wave transforms (no barriers)
+    (70001, 10, 200, 1024, 333),      # N = 1024, odd hop, even K
 ]
 
 
