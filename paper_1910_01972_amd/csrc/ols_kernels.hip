@@ -455,16 +455,22 @@ __global__ void ols_ds_fixup_kernel(const float2* __restrict__ ws_ds, float2* __
   const int64_t t = ub / K;
   if (first_unit(U, P, b - 1) > t * K) return;
   const int64_t blo = owner_of_unit(U, P, t * K), bhi = owner_of_unit(U, P, (t + 1) * K - 1);
-  for (int i = threadIdx.x; i < GE::SEGS * H; i += blockDim.x) {
-    const int sg = i / H, p = i - sg * H;
-    const int64_t o = (t * GE::SEGS + sg) * H + p;
-    if (o >= Ns) continue;
-    float2 a = make_float2(0.f, 0.f);
-    for (int64_t bb = blo; bb <= bhi; ++bb) {
-      const int slot = first_unit(U, P, bb) / K == t ? 0 : 1;
-      a = cadd(a, ws_ds[((bb * 2 + slot) * GE::SEGS + sg) * (int64_t)N + p]);
+  // Slot of each sharing workgroup's window (0: the tile is its first, 1: its
+  // last): every workgroup after blo starts inside tile t; blo may have
+  // started in an earlier tile.  Hoisted out of the element loop (64-bit
+  // divisions).
+  const int64_t slot_lo = first_unit(U, P, blo) / K == t ? 0 : 1;
+  for (int sg = 0; sg < GE::SEGS; ++sg) {
+    const int64_t o0 = (t * GE::SEGS + sg) * H;
+    for (int p = threadIdx.x; p < H; p += blockDim.x) {
+      if (o0 + p >= Ns) break;
+      float2 a = make_float2(0.f, 0.f);
+      for (int64_t bb = blo; bb <= bhi; ++bb) {
+        const int64_t slot = bb == blo ? slot_lo : 0;
+        a = cadd(a, ws_ds[((bb * 2 + slot) * GE::SEGS + sg) * (int64_t)N + p]);
+      }
+      ds[o0 + p] = a;
     }
-    ds[o] = a;
   }
 }
 
