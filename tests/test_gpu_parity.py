@@ -288,3 +288,35 @@ def test_sweep_cells_sampled(ols, cell):
     rel, n = sampled_check(ols, wl, N=0, windows=8)
     say(f"  {wl.name}: max rel {rel.max():.3e}")
     assert np.all(rel <= TOL), rel
+
+
+def test_signal_longer_than_2p31_sampled(ols):
+    """N_s = 2^31 + 4099 samples, 2 filters (outputs beyond 2^32 elements):
+    64-bit indexing end to end; sampled outputs against eq. (1) at indices
+    around 2^31, the segment edges there and the end."""
+    Ns, K, M, N = (1 << 31) + 4099, 2, 33, 512
+    say(f"huge Ns={Ns} K={K} M={M} N={N}")
+    _, h = workloads.make_signal_filters(1, K, M, seed=2024)
+    s = torch.empty(Ns, dtype=torch.complex64, device="cuda")
+    step = 1 << 28
+    for a in range(0, Ns, step):
+        s[a:min(Ns, a + step)] = workloads.exact_signal(a, min(Ns, a + step), "cuda")
+    plan = ols.OLSPlan(dev(h), N=N)
+    H = plan.info()["H"]
+    y = plan.forward(s)
+    torch.cuda.synchronize()
+    j = (1 << 31) // H
+    idx = np.unique(np.concatenate([np.arange(0, 50), np.arange((1 << 31) - 40, (1 << 31) + 40),
+                                    np.arange(j * H - 3, j * H + 3), np.arange(Ns - 60, Ns)]))
+    got = y[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    del y, s
+    torch.cuda.empty_cache()
+    # the oracle sees the same exact values, rebuilt on the host window by window
+    ref = np.zeros((K, idx.size), dtype=np.complex128)
+    for c, n0 in enumerate(idx):
+        w0 = max(0, int(n0) - M + 1)
+        win = workloads.exact_signal(w0, int(n0) + 1, "cpu").numpy().astype(np.complex128)
+        ref[:, c] = conv.direct_conv_at(win, h, [int(n0) - w0])[:, 0]
+    rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert np.all(rel <= TOL), rel
+    plan.close()

@@ -245,3 +245,17 @@ def test_real_conv_at_and_complex_agreement():
     yc = conv.direct_conv(s.astype(complex), h.astype(complex))
     P._close(yc.real, y, 1e-12, "complex path real part")
     assert np.abs(yc.imag).max() == 0.0
+
+
+def test_exact_signal_generator_is_window_consistent():
+    """The long-signal generator rebuilds any window identically (it is used
+    for the GPU input and, window by window, for the oracle's)."""
+    pytest.importorskip("torch")
+    full = workloads.exact_signal(0, 5000).numpy()
+    assert full.dtype == np.complex64
+    for a, b in ((0, 10), (1234, 1300), (4990, 5000)):
+        assert np.array_equal(workloads.exact_signal(a, b).numpy(), full[a:b])
+    big = workloads.exact_signal((1 << 31) - 2, (1 << 31) + 2).numpy()
+    n = np.arange((1 << 31) - 2, (1 << 31) + 2, dtype=np.int64)
+    want = ((n * 40503) % (1 << 20)) / (1 << 20) - 0.5 + 1j * (((n * 65537) % (1 << 20)) / (1 << 20) - 0.5)
+    assert np.array_equal(big.astype(np.complex128), want)

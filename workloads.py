@@ -76,6 +76,19 @@ def make_real_signal_filters(Ns: int, K: int, M: int, seed: int):
     return s, h
 
 
+def exact_signal(start: int, stop: int, device="cpu"):
+    """Samples start .. stop-1 of a long deterministic complex64 signal,
+    s[n] = ((n*40503) mod 2^20)/2^20 - 1/2 + i (((n*65537) mod 2^20)/2^20 - 1/2):
+    integer arithmetic and exactly representable float32 values, so any window
+    is rebuilt bit for bit from n alone, on any device (for signals too long to
+    draw on the host)."""
+    import torch
+    n = torch.arange(start, stop, dtype=torch.int64, device=device)
+    re = ((n * 40503) % (1 << 20)).to(torch.float32) / (1 << 20) - 0.5
+    im = ((n * 65537) % (1 << 20)).to(torch.float32) / (1 << 20) - 0.5
+    return torch.complex(re, im)
+
+
 def make_grad(K: int, Ns: int, seed: int):
     """Upstream gradient dL/dy, complex64 [K, Ns], real/imag i.i.d. N(0, 1).
 
