@@ -115,7 +115,7 @@ std::vector<std::array<float2, Geo<N>::TWR>> lane_twiddles(const std::vector<flo
   return tw;
 }
 
-// Filter spectra in kernel order F[K][16][G] (as the device plan stores them).
+// Filter spectra in kernel order F[K][8][G][2] (as the device plan stores them).
 template <int N>
 std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<float2>& table, bool* guards,
                             bool diff = false, bool real = false) {
@@ -473,7 +473,7 @@ struct RunSpec {
     for (int r = 0; r < K; ++r)
       for (int reg = 0; reg < 16; ++reg)
         for (int g = 0; g < Geo<N>::G; ++g)
-          out[(int64_t)r * N + spectrum_index<N>(g, reg)] = F[(int64_t)r * N + reg * Geo<N>::G + g];
+          out[(int64_t)r * N + spectrum_index<N>(g, reg)] = F[(int64_t)r * N + spectrum_offset<N>(reg, g)];
     return guards ? 0 : 2;
   }
 };

@@ -151,15 +151,16 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const vo
   if (valid) store_spectrum<N>(x, F, r, g, 1.0f / (float)N);
 }
 
-// Natural-order copy of the spectra: out[r][k] = F[r][reg][g] with
-// k = spectrum_index(g, reg).
+// Natural-order copy of the spectra: out[r][k] = F[r][spectrum_offset(reg, g)]
+// with k = spectrum_index(g, reg).
 template <int N>
 __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, float2* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // over K * N
   if (i >= (int64_t)K * N) return;
   const int r = (int)(i / N);
-  const int rem = (int)(i - (int64_t)r * N);
-  const int reg = rem / Geo<N>::G, g = rem - reg * Geo<N>::G;
+  const int rem = (int)(i - (int64_t)r * N);  // = spectrum_offset(reg, g)
+  const int pair = rem >> 1, j = pair / Geo<N>::G, g = pair - j * Geo<N>::G;
+  const int reg = 2 * j + (rem & 1);
   out[(int64_t)r * N + spectrum_index<N>(g, reg)] = F[i];
 }
 
