@@ -127,6 +127,16 @@ OLS_HD void spectrum_product(float2 (&x)[16], const float2 (&A)[16], const float
 // past-the-end positions (a negative offset wraps to a huge unsigned one),
 // with no per-lane compare or branch.  Smaller transforms share a wave
 // between segments and use per-lane predicates.
+//
+// Non-temporal stores only pay for whole 64-byte granules.  A granule that
+// one store instruction covers only in part (rows of complex outputs whose
+// length N_s is not a multiple of 8 start off the 64-byte grid; so can a
+// segment edge) is written with the default policy instead, so that its two
+// partial writes can merge in L2 before they go to HBM: with non-temporal
+// partial writes the forward kernel ran 1.5-1.75x slower when its rows were
+// off the grid, with the split policy 1.15x.  The batched kernel keeps
+// non-temporal stores throughout: its per-lane stores measured faster that
+// way on rows of uneven length.
 // How a kernel writes its outputs: plain per-lane predicated stores,
 // non-temporal predicated stores, or non-temporal buffer stores (G >= 64;
 // other sizes fall back to predicated non-temporal stores).  Kernels near
@@ -159,16 +169,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(void* base, int bytes
   return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, 0x00020000);
 }
 
-__device__ __forceinline__ void buffer_store_nt(float2 v, __amdgpu_buffer_rsrc_t rs, int off) {
+template <int CPOL>
+__device__ __forceinline__ void buffer_store(float2 v, __amdgpu_buffer_rsrc_t rs, int off) {
   typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
   u32x2 d;
   d.x = __float_as_uint(v.x);
   d.y = __float_as_uint(v.y);
-  __builtin_amdgcn_raw_buffer_store_b64(d, rs, off, 0, CPOL_NT);
+  __builtin_amdgcn_raw_buffer_store_b64(d, rs, off, 0, CPOL);
 }
 
-__device__ __forceinline__ void buffer_store_nt(float v, __amdgpu_buffer_rsrc_t rs, int off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, 0, CPOL_NT);
+template <int CPOL>
+__device__ __forceinline__ void buffer_store(float v, __amdgpu_buffer_rsrc_t rs, int off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, 0, CPOL);
 }
 #endif
 
@@ -178,22 +190,47 @@ OLS_HD int kept_count(int64_t Ns, int64_t out0, int H) {
   return rem >= H ? H : (rem < 0 ? 0 : (int)rem);
 }
 
-// After the inverse transform register reg of lane g holds circular position
-// p = g + time_pos_const(reg).  Positions D .. D+H-1 are unaliased
-// (D >= M-1, sec. 3.2) and go to outputs out0 + p - D, out0 = j*H; outputs
-// >= N_s are not written.  F maps the transform value to the stored one (the
-// identity, or the power epilogue of sec. 4 with a float output).
-template <int N, int MODE, typename T, typename F>
-OLS_HD void store_kept(const float2 (&x)[16], T* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H, int g,
-                       F f) {
+// Position of an element inside its 64-byte granule, in elements.
+template <typename T>
+OLS_HD int granule_phase(const T* p) {
+  return (int)(((uintptr_t)p / sizeof(T)) & (64 / sizeof(T) - 1));
+}
+
+// Stores of one segment's kept outputs.  After the inverse transform register
+// reg of lane g holds circular position p = g + time_pos_const(reg); positions
+// D .. D+H-1 are unaliased (D >= M-1, sec. 3.2) and go to outputs
+// out0 + p - D, out0 = j*H; outputs >= N_s are not written.  val(reg) gives
+// the value stored from register reg.
+//
+// Buffer stores (G >= 64): one store instruction writes 64 consecutive
+// positions (lane l = g mod 64 of a chunk that starts on a multiple of 64;
+// time_pos_const is a multiple of G).  The phase c of a lane's output inside
+// its 64-byte granule (LS outputs) is the same in every register, so whether
+// the chunk holds the lane's whole granule (l - c >= 0 and l - c + LS <= 64)
+// is a property of the lane: those lanes store non-temporally, the others
+// (the partial granules at the two ends of each chunk when the row is off
+// the 64-byte grid) with the default policy.  The first and last granule of
+// a segment are partial when they share a granule with the neighbouring
+// segment; the chunk test sees that exactly when the segment starts on a
+// chunk boundary (D a multiple of 64), otherwise the head granule may go
+// non-temporal, one granule in H / LS.
+template <int N, int MODE, typename T, typename V>
+OLS_HD void store_segment(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H, int g, V val) {
   const int cnt = kept_count(Ns, out0, H);
 #if defined(__HIP_DEVICE_COMPILE__)
   if constexpr (MODE == STORE_NT_BUFFER && Geo<N>::G >= 64) {
+    constexpr int LS = 64 / (int)sizeof(T);  // outputs per 64-byte granule
+    const int l = g & 63;
+    const int c = (granule_phase(yrow + out0) + g - D) & (LS - 1);
     const __amdgpu_buffer_rsrc_t rs = out_rsrc(yrow + out0, cnt * (int)sizeof(T));
+    if (l >= c && l - c + LS <= 64) {
 #pragma unroll
-    for (int reg = 0; reg < 16; ++reg) {
-      const int p = g + time_pos_const<N>(reg);
-      buffer_store_nt(f(x[reg]), rs, (p - D) * (int)sizeof(T));
+      for (int reg = 0; reg < 16; ++reg)
+        buffer_store<CPOL_NT>(val(reg), rs, (g + time_pos_const<N>(reg) - D) * (int)sizeof(T));
+    } else {
+#pragma unroll
+      for (int reg = 0; reg < 16; ++reg)
+        buffer_store<0>(val(reg), rs, (g + time_pos_const<N>(reg) - D) * (int)sizeof(T));
     }
     return;
   }
@@ -202,8 +239,16 @@ OLS_HD void store_kept(const float2 (&x)[16], T* __restrict__ yrow, int64_t Ns, 
 #pragma unroll
   for (int reg = 0; reg < 16; ++reg) {
     const int p = g + time_pos_const<N>(reg);
-    if (p >= D && p < D + cnt) out_store<MODE>(base + p, f(x[reg]));
+    if (p >= D && p < D + cnt) out_store<MODE>(base + p, val(reg));
   }
+}
+
+// F maps the transform value to the stored one (the identity, or the power
+// epilogue of sec. 4 with a float output).
+template <int N, int MODE, typename T, typename F>
+OLS_HD void store_kept(const float2 (&x)[16], T* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H, int g,
+                       F f) {
+  store_segment<N, MODE>(yrow, Ns, out0, D, H, g, [&](int reg) { return f(x[reg]); });
 }
 
 struct Identity {
@@ -286,29 +331,10 @@ OLS_HD void zero_lags(float2* __restrict__ part, int M, int g) {
 template <int N, bool POWER, int MODE = STORE_PLAIN>
 OLS_HD void store_valid_pair(const float2 (&x)[16], float* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H,
                              int g) {
-  const int cnt_a = kept_count(Ns, out0, H), cnt_b = kept_count(Ns, out0 + H, H);
-#if defined(__HIP_DEVICE_COMPILE__)
-  if constexpr (MODE == STORE_NT_BUFFER && Geo<N>::G >= 64) {
-    const __amdgpu_buffer_rsrc_t ra = out_rsrc(yrow + out0, cnt_a * 4);
-    const __amdgpu_buffer_rsrc_t rb = out_rsrc(yrow + out0 + H, cnt_b * 4);
-#pragma unroll
-    for (int reg = 0; reg < 16; ++reg) {
-      const int off = (g + time_pos_const<N>(reg) - D) * 4;
-      buffer_store_nt(POWER ? x[reg].x * x[reg].x : x[reg].x, ra, off);
-      buffer_store_nt(POWER ? x[reg].y * x[reg].y : x[reg].y, rb, off);
-    }
-    return;
-  }
-#endif
-  float* base = yrow + (out0 - D);
-#pragma unroll
-  for (int reg = 0; reg < 16; ++reg) {
-    const int p = g + time_pos_const<N>(reg);
-    const float a = POWER ? x[reg].x * x[reg].x : x[reg].x;
-    const float b = POWER ? x[reg].y * x[reg].y : x[reg].y;
-    if (p >= D && p < D + cnt_a) out_store<MODE>(base + p, a);
-    if (p >= D && p < D + cnt_b) out_store<MODE>(base + H + p, b);
-  }
+  store_segment<N, MODE>(yrow, Ns, out0, D, H, g,
+                         [&](int reg) { return POWER ? x[reg].x * x[reg].x : x[reg].x; });
+  store_segment<N, MODE>(yrow, Ns, out0 + H, D, H, g,
+                         [&](int reg) { return POWER ? x[reg].y * x[reg].y : x[reg].y; });
 }
 
 // Filters per work unit of the forward kernels: two interleaved transforms

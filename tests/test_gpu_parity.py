@@ -262,6 +262,19 @@ def test_filter_bank_2p23_sampled(ols):
     assert np.all(rel <= TOL), rel
 
 
+@pytest.mark.parametrize("extra", [1, 4, 8])
+def test_filter_bank_off_grid_rows_sampled(ols, extra):
+    """The benchmark filter bank with N_s = 2^23 + extra: rows of the output
+    start 8, 32 or 64 bytes off the 64-byte grid, so part of every store goes
+    through the default-policy branch.  Guards around y, sampled outputs."""
+    import dataclasses
+    wl = workloads.WORKLOADS["filter_bank_2p23_k32_m256"]
+    wl = dataclasses.replace(wl, Ns=wl.Ns + extra)
+    rel, n = sampled_check(ols, wl, windows=8)
+    say(f"  filter_bank 2^23+{extra}: {n} sampled outputs per row, max rel L2 {rel.max():.3e}")
+    assert np.all(rel <= TOL), rel
+
+
 def test_filter_bank_2p23_prefix_full(ols):
     """Full comparison of the first 2^16 outputs of every row, in the same
     plan and launch configuration as the benchmark."""

@@ -59,6 +59,11 @@ CASES = [
     (30000, 3, 1000, 4096, True, True),
     (40000, 2, 2000, 8192, True, False),
     (100001, 16, 64, 512, False, True),
+    # rows off the 64-byte grid (N_s not a multiple of 8 / 16) on whole-wave transforms
+    (20003, 3, 100, 1024, True, True),
+    (30001, 2, 700, 2048, False, True),
+    (40005, 3, 1000, 4096, True, False),
+    (50001, 2, 2000, 8192, False, True),
 ]
 
 

@@ -61,6 +61,10 @@ CASES = [
     (40000, 8, 1500, 4096, False, False),
     (40000, 2, 700, 8192, True, True),
     (100001, 16, 64, 512, False, False),
+    # rows off the 64-byte grid (N_s not a multiple of 16) on whole-wave transforms
+    (20001, 3, 300, 2048, False, False),
+    (30005, 4, 1000, 4096, False, True),
+    (40003, 2, 700, 8192, False, False),
 ]
 
 
