@@ -578,25 +578,43 @@ int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t
     const int segs = 4096 / it.N;
     const int64_t nseg = (it.Ns + it.H - 1) / it.H;
     it.ntiles = (nseg + segs - 1) / segs;
-    it.unit_begin = units;
     it.units = it.ntiles * ((it.K + it.nf - 1) / it.nf);
+    if (dispatch<SpecN>(it.N, &it, (const float2*)h[i]) != 0) return 2;
+  }
+  // the plan's kernel order: items by class (N, filters per unit), stable
+  std::stable_sort(items.begin(), items.end(), [](const EmuItem& u, const EmuItem& v) {
+    return u.N != v.N ? u.N < v.N : u.nf < v.nf;
+  });
+  for (EmuItem& it : items) {
+    it.unit_begin = units;
     units += it.units;
     it.tile_begin = tiles;
     tiles += it.ntiles;
-    if (dispatch<SpecN>(it.N, &it, (const float2*)h[i]) != 0) return 2;
   }
-  // the device schedule: tiles of all items dealt round-robin to the grid
+  // the device schedule: tiles of all items dealt round-robin to the grid,
+  // each workgroup taking its tiles in runs of one class
   const int64_t P = tiles < grid ? tiles : grid;
   for (int64_t b = 0; b < P; ++b) {
     int i = 0;
-    for (int64_t t = b; t < tiles; t += P) {
+    int64_t t = b;
+    int runs = 0;
+    while (t < tiles) {
       while (i + 1 < n && items[i + 1].tile_begin <= t) ++i;
-      EmuItem& it = items[i];
-      if (t < it.tile_begin || t >= it.tile_begin + it.ntiles) return 4;  // walk invariant
-      const int64_t per_tile = it.units / it.ntiles;
-      const int64_t a = (t - it.tile_begin) * per_tile;
-      if (dispatch<RangeN>(it.N, &it, a, a + per_tile) != 0) return 3;
+      const int N = items[i].N, nf = items[i].nf;
+      ++runs;
+      for (;;) {
+        EmuItem& it = items[i];
+        if (t < it.tile_begin || t >= it.tile_begin + it.ntiles) return 4;  // walk invariant
+        const int64_t per_tile = it.units / it.ntiles;
+        const int64_t a = (t - it.tile_begin) * per_tile;
+        if (dispatch<RangeN>(it.N, &it, a, a + per_tile) != 0) return 3;
+        t += P;
+        if (t >= tiles) break;
+        while (i + 1 < n && items[i + 1].tile_begin <= t) ++i;
+        if (items[i].N != N || items[i].nf != nf) break;
+      }
     }
+    if (runs > 10) return 5;  // at most one run per class (5 lengths x 2)
   }
   (void)units;
   return 0;

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/ols.h"
@@ -176,19 +177,17 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
 // REAL (R2R): s and y are float32 and a transform carries a pair of segments
 // (real part 2q, imaginary part 2q+1), so a tile is SEGS pairs.  POWER
 // stores |y|^2 (float32) instead of y.
+// tw: this lane's twiddles (load_lane_twiddles).
 template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_BUFFER>
-__device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
+__device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
-                                              const float2* __restrict__ twt, int64_t u0, int64_t u1, float2* lds,
+                                              const float2 (&tw)[Geo<N>::TWR], int64_t u0, int64_t u1, float2* lds,
                                               int& par) {
   using GE = Geo<N>;
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
   const int KG = (K + NF - 1) / NF;  // filter groups
   const int64_t step = REAL ? 2 * (int64_t)H : H;  // signal advance per transform
-
-  float2 tw[GE::TWR];
-  load_lane_twiddles<N>(tw, twt, g);
 
   int64_t tile = u0 / KG;
   int rg = (int)(u0 - tile * KG);
@@ -245,6 +244,16 @@ __device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64
   }
 }
 
+template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_BUFFER>
+__device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
+                                              void* __restrict__ yv, int K, int D, int H,
+                                              const float2* __restrict__ twt, int64_t u0, int64_t u1, float2* lds,
+                                              int& par) {
+  float2 tw[Geo<N>::TWR];
+  load_lane_twiddles<N>(tw, twt, threadIdx.x % Geo<N>::G);
+  forward_units<N, NF, POWER, REAL, SMODE>(sv, Ns, F, yv, K, D, H, tw, u0, u1, lds, par);
+}
+
 template <int N, int NF, bool POWER, bool REAL>
 __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const void* __restrict__ s, int64_t Ns,
                                                                  const float2* __restrict__ F, void* __restrict__ y,
@@ -285,11 +294,32 @@ struct BatchItem {
 
 // Each (N, filters per unit) body is its own non-inlined function, so its
 // registers are allocated on their own and the kernel needs only the
-// maximum, not the sum, over the branches it may take.
+// maximum, not the sum, over the branches it may take.  A body runs the
+// workgroup's tiles t, t + P, t + 2P, ... for as long as their items keep its
+// (N, filters per unit): the lane twiddles are loaded once per run, and
+// consecutive tiles of one class need no barrier between them (the same
+// exchange protocol as consecutive tiles of the single-signal kernel).  The
+// batch plan orders the items by class, so a workgroup meets each class in
+// one run.  Returns the workgroup's first tile of another class (or past the
+// end); i follows the item walk.
 template <int N, int NF>
-__device__ __attribute__((noinline)) void batched_item_range(const BatchItem& it, const float2* twt, int64_t a,
-                                                             int64_t b, float2* lds, int& par) {
-  forward_range<N, NF, false, false, STORE_NT>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, twt, a, b, lds, par);
+__device__ __attribute__((noinline)) int64_t batched_run(const BatchItem* __restrict__ items, int nitems, int& i,
+                                                         int64_t t, int64_t total_tiles,
+                                                         const float2* __restrict__ twt, float2* lds, int& par) {
+  float2 tw[Geo<N>::TWR];
+  load_lane_twiddles<N>(tw, twt, threadIdx.x % Geo<N>::G);
+  for (;;) {
+    const BatchItem& it = items[i];
+    const int64_t per_tile = it.units / it.ntiles;
+    const int64_t a = (t - it.tile_begin) * per_tile;
+    forward_units<N, NF, false, false, STORE_NT>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a,
+                                                  a + per_tile, lds, par);
+    t += gridDim.x;
+    if (t >= total_tiles) return t;
+    // t grows, so the item walk only moves forward (items without tiles are skipped)
+    while (i + 1 < nitems && items[i + 1].tile_begin <= t) ++i;
+    if (items[i].N != N || items[i].nf != NF) return t;
+  }
 }
 
 // Two filters per unit only up to N = 2048 here (BATCH_NF2_MAX_N): the
@@ -297,18 +327,16 @@ __device__ __attribute__((noinline)) void batched_item_range(const BatchItem& it
 // function, which would drop the whole kernel to one wave per SIMD.
 
 template <int N>
-__device__ __forceinline__ void batched_item(const BatchItem& it, const float2* twt, int64_t a, int64_t b,
-                                             float2* lds, int& par) {
+__device__ __forceinline__ int64_t batched_class(const BatchItem* __restrict__ items, int nitems, int& i, int64_t t,
+                                                 int64_t total_tiles, const float2* __restrict__ twt, float2* lds,
+                                                 int& par) {
   if constexpr (N <= BATCH_NF2_MAX_N) {
-    if (it.nf == 2) {
-      batched_item_range<N, 2>(it, twt, a, b, lds, par);
-      return;
-    }
+    if (items[i].nf == 2) return batched_run<N, 2>(items, nitems, i, t, total_tiles, twt, lds, par);
   }
-  batched_item_range<N, 1>(it, twt, a, b, lds, par);
+  return batched_run<N, 1>(items, nitems, i, t, total_tiles, twt, lds, par);
 }
 
-__global__ __launch_bounds__(256) void ols_batched_kernel(const BatchItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ols_batched_kernel(const BatchItem* __restrict__ items, int nitems,
                                                           int64_t total_tiles, const float2* __restrict__ tw256,
                                                           const float2* __restrict__ tw512,
                                                           const float2* __restrict__ tw1024,
@@ -316,31 +344,28 @@ __global__ __launch_bounds__(256) void ols_batched_kernel(const BatchItem* __res
                                                           const float2* __restrict__ tw4096) {
   __shared__ float2 lds[2 * Geo<4096>::LDS];
   static_assert(Geo<256>::LDS == Geo<4096>::LDS && Geo<2048>::LDS == Geo<4096>::LDS, "same LDS footprint");
-  // Tiles of all items, in item order, dealt round-robin to the workgroups:
-  // workgroup b takes tiles b, b + P, b + 2P, ... with all of each tile's
-  // filters.  At any moment the whole grid works on neighbouring tiles of one
-  // or two items, so every XCD keeps those items' filter spectra in its L2
-  // (balanced contiguous unit ranges spread the grid over all items at once
-  // and re-read the spectra from HBM: 19 % slower on the uneven batch).  The
-  // imbalance is at most one tile per workgroup.
+  // Tiles of all items, in the plan's item order, dealt round-robin to the
+  // workgroups: workgroup b takes tiles b, b + P, b + 2P, ... with all of
+  // each tile's filters.  At any moment the whole grid works on neighbouring
+  // tiles of one or two items, so every XCD keeps those items' filter
+  // spectra in its L2 (balanced contiguous unit ranges spread the grid over
+  // all items at once and re-read the spectra from HBM: 19 % slower on the
+  // uneven batch).  The imbalance is at most one tile per workgroup.
   int par = 0;
   int i = 0;
-  for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-    // t grows, so the item walk only moves forward (items without tiles are skipped)
+  int64_t t = blockIdx.x;
+  while (t < total_tiles) {
     while (i + 1 < nitems && items[i + 1].tile_begin <= t) ++i;
-    const BatchItem it = items[i];
-    const int64_t per_tile = it.units / it.ntiles;
-    const int64_t a = (t - it.tile_begin) * per_tile, b = a + per_tile;
-    // items of different N lay out the LDS buffers differently, and
+    // items of another class lay out the LDS buffers differently, and
     // single-wave transforms exchange without barriers: every wave must have
-    // finished with the previous tile's buffers
+    // finished with the previous run's buffers
     __syncthreads();
-    switch (it.N) {
-      case 256: batched_item<256>(it, tw256, a, b, lds, par); break;
-      case 512: batched_item<512>(it, tw512, a, b, lds, par); break;
-      case 1024: batched_item<1024>(it, tw1024, a, b, lds, par); break;
-      case 2048: batched_item<2048>(it, tw2048, a, b, lds, par); break;
-      default: batched_item<4096>(it, tw4096, a, b, lds, par); break;
+    switch (items[i].N) {
+      case 256: t = batched_class<256>(items, nitems, i, t, total_tiles, tw256, lds, par); break;
+      case 512: t = batched_class<512>(items, nitems, i, t, total_tiles, tw512, lds, par); break;
+      case 1024: t = batched_class<1024>(items, nitems, i, t, total_tiles, tw1024, lds, par); break;
+      case 2048: t = batched_class<2048>(items, nitems, i, t, total_tiles, tw2048, lds, par); break;
+      default: t = batched_class<4096>(items, nitems, i, t, total_tiles, tw4096, lds, par); break;
     }
   }
 }
@@ -540,8 +565,10 @@ struct ols_batch_s {
   int64_t total_units = 0;
   int grid = 0;
   int cus = 0;
-  BatchItem* items_dev = nullptr;
-  std::vector<BatchItem> items_host;
+  BatchItem* items_dev = nullptr;       // in kernel order (items_sorted)
+  std::vector<BatchItem> items_host;    // in the caller's order
+  std::vector<BatchItem> items_sorted;  // by class (N, filters per unit)
+  std::vector<int> order;               // items_sorted[k] = items_host[order[k]]
   float2* spectra = nullptr;
   float2* tw[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // N = 256 .. 4096
   int64_t total_tiles = 0;
@@ -1114,14 +1141,25 @@ ols_status_t ols_batch_plan(ols_batch_t* out, const ols_batch_item_t* items, int
       d.nf = choose_nf_batched(N, it.K);
       const int segs = 4096 / N;  // transforms per 256-thread workgroup
       const int64_t nseg = (it.N_s + d.H - 1) / d.H;
-      const int64_t ntiles = (nseg + segs - 1) / segs;
+      d.ntiles = (nseg + segs - 1) / segs;
+      d.units = d.ntiles * ((it.K + d.nf - 1) / d.nf);
+      spec_elems += (size_t)it.K * N;
+    }
+    // The kernel's tile list takes the items by class (N, filters per unit),
+    // in the caller's order within a class, so that each workgroup meets
+    // each class in one run of tiles.
+    b->order.resize(n);
+    for (int i = 0; i < n; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+      const BatchItem &u = b->items_host[x], &v = b->items_host[y];
+      return u.N != v.N ? u.N < v.N : u.nf < v.nf;
+    });
+    for (int k = 0; k < n; ++k) {
+      BatchItem& d = b->items_host[b->order[k]];
       d.unit_begin = units;
-      d.units = ntiles * ((it.K + d.nf - 1) / d.nf);
       units += d.units;
       d.tile_begin = b->total_tiles;
-      d.ntiles = ntiles;
-      b->total_tiles += ntiles;
-      spec_elems += (size_t)it.K * N;
+      b->total_tiles += d.ntiles;
     }
     b->total_units = units;
     hipError_t e;
@@ -1150,8 +1188,10 @@ ols_status_t ols_batch_plan(ols_batch_t* out, const ols_batch_item_t* items, int
       e = dispatch<RunSpectra>(d.N, items[i].h, d.K, d.M, F, (const float2*)b->tw[k], st, 0, 0);
       if (e != hipSuccess) { destroy_batch(b); return hip_fail(e, "filter spectra launch"); }
     }
+    b->items_sorted.resize(n);
+    for (int k = 0; k < n; ++k) b->items_sorted[k] = b->items_host[b->order[k]];
     if (hipMalloc(&b->items_dev, (size_t)n * sizeof(BatchItem)) != hipSuccess) { destroy_batch(b); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "item table allocation"); }
-    if ((e = hipMemcpyAsync(b->items_dev, b->items_host.data(), (size_t)n * sizeof(BatchItem), hipMemcpyHostToDevice, st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "item table upload"); }
+    if ((e = hipMemcpyAsync(b->items_dev, b->items_sorted.data(), (size_t)n * sizeof(BatchItem), hipMemcpyHostToDevice, st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "item table upload"); }
     if ((e = hipStreamSynchronize(st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "batch plan synchronisation"); }
     *out = b;
     return OLS_SUCCESS;
