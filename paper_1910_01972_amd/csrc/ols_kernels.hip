@@ -178,7 +178,7 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
 // (real part 2q, imaginary part 2q+1), so a tile is SEGS pairs.  POWER
 // stores |y|^2 (float32) instead of y.
 // tw: this lane's twiddles (load_lane_twiddles).
-template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_BUFFER>
+template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE>
 __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2 (&tw)[Geo<N>::TWR], int64_t u0, int64_t u1, float2* lds,
@@ -244,7 +244,7 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
   }
 }
 
-template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_BUFFER>
+template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE>
 __device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2* __restrict__ twt, int64_t u0, int64_t u1, float2* lds,

@@ -138,10 +138,10 @@ OLS_HD void spectrum_product(float2 (&x)[16], const float2 (&A)[16], const float
 // non-temporal stores throughout: its per-lane stores measured faster that
 // way on rows of uneven length.
 // How a kernel writes its outputs: plain per-lane predicated stores,
-// non-temporal predicated stores, or non-temporal buffer stores (G >= 64;
-// other sizes fall back to predicated non-temporal stores).  Kernels near
-// the register limit keep the cheaper forms.
-enum StoreMode { STORE_PLAIN = 0, STORE_NT = 1, STORE_NT_BUFFER = 2 };
+// non-temporal predicated stores, or non-temporal stores for whole granules
+// only (buffer stores when G >= 64, predicated ones otherwise).  Kernels
+// near the register limit keep the cheaper forms.
+enum StoreMode { STORE_PLAIN = 0, STORE_NT = 1, STORE_NT_WHOLE = 2 };
 
 template <int MODE, typename T>
 OLS_HD void out_store(T* p, T v) {
@@ -202,28 +202,32 @@ OLS_HD int granule_phase(const T* p) {
 // out0 + p - D, out0 = j*H; outputs >= N_s are not written.  val(reg) gives
 // the value stored from register reg.
 //
-// Buffer stores (G >= 64): one store instruction writes 64 consecutive
-// positions (lane l = g mod 64 of a chunk that starts on a multiple of 64;
-// time_pos_const is a multiple of G).  The phase c of a lane's output inside
-// its 64-byte granule (LS outputs) is the same in every register, so whether
-// the chunk holds the lane's whole granule (l - c >= 0 and l - c + LS <= 64)
-// is a property of the lane: those lanes store non-temporally, the others
-// (the partial granules at the two ends of each chunk when the row is off
-// the 64-byte grid) with the default policy.  The first and last granule of
-// a segment are partial when they share a granule with the neighbouring
-// segment; the chunk test sees that exactly when the segment starts on a
-// chunk boundary (D a multiple of 64), otherwise the head granule may go
-// non-temporal, one granule in H / LS.
+// STORE_NT_WHOLE: one store instruction writes C = min(G, 64) consecutive
+// positions of a segment (lane l = g mod C of a chunk that starts on a
+// multiple of C; time_pos_const is a multiple of G, and of LS, the outputs
+// per 64-byte granule).  The phase c of a lane's output inside its granule
+// is therefore the same in every register, so whether the chunk holds the
+// lane's whole granule (l - c >= 0 and l - c + LS <= C) is a property of the
+// lane: those lanes store non-temporally, the others (the partial granules
+// at the two ends of each chunk when the row is off the 64-byte grid) with
+// the default policy.  The first and last granule of a segment are partial
+// when they share a granule with the neighbouring segment; the chunk test
+// sees that exactly when the segment starts on a chunk boundary (D a
+// multiple of C), otherwise the head granule may go non-temporal, one
+// granule in H / LS.
 template <int N, int MODE, typename T, typename V>
 OLS_HD void store_segment(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H, int g, V val) {
+  constexpr int LS = 64 / (int)sizeof(T);                // outputs per 64-byte granule
+  constexpr int C = Geo<N>::G < 64 ? Geo<N>::G : 64;     // positions per store instruction
+  static_assert(C % LS == 0, "chunks hold whole granules");
   const int cnt = kept_count(Ns, out0, H);
+  const int l = g & (C - 1);
+  const int c = (granule_phase(yrow + out0) + g - D) & (LS - 1);
+  const bool whole = l >= c && l - c + LS <= C;
 #if defined(__HIP_DEVICE_COMPILE__)
-  if constexpr (MODE == STORE_NT_BUFFER && Geo<N>::G >= 64) {
-    constexpr int LS = 64 / (int)sizeof(T);  // outputs per 64-byte granule
-    const int l = g & 63;
-    const int c = (granule_phase(yrow + out0) + g - D) & (LS - 1);
+  if constexpr (MODE == STORE_NT_WHOLE && Geo<N>::G >= 64) {
     const __amdgpu_buffer_rsrc_t rs = out_rsrc(yrow + out0, cnt * (int)sizeof(T));
-    if (l >= c && l - c + LS <= 64) {
+    if (whole) {
 #pragma unroll
       for (int reg = 0; reg < 16; ++reg)
         buffer_store<CPOL_NT>(val(reg), rs, (g + time_pos_const<N>(reg) - D) * (int)sizeof(T));
@@ -236,10 +240,18 @@ OLS_HD void store_segment(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D,
   }
 #endif
   T* base = yrow + (out0 - D);
+  if (MODE == STORE_NT || (MODE == STORE_NT_WHOLE && whole)) {
 #pragma unroll
-  for (int reg = 0; reg < 16; ++reg) {
-    const int p = g + time_pos_const<N>(reg);
-    if (p >= D && p < D + cnt) out_store<MODE>(base + p, val(reg));
+    for (int reg = 0; reg < 16; ++reg) {
+      const int p = g + time_pos_const<N>(reg);
+      if (p >= D && p < D + cnt) out_store<STORE_NT>(base + p, val(reg));
+    }
+  } else {
+#pragma unroll
+    for (int reg = 0; reg < 16; ++reg) {
+      const int p = g + time_pos_const<N>(reg);
+      if (p >= D && p < D + cnt) out_store<STORE_PLAIN>(base + p, val(reg));
+    }
   }
 }
 
