@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,10 +33,19 @@ KERNEL_SOURCES = ("ols_kernels.hip", "ols_fft.hpp", "ols_ops.hpp", "ols_twiddle.
 HOST_MARKER = b"// Host side"
 
 
+def _code_tokens(data: bytes) -> bytes:
+    """C++ source without comments and with whitespace runs collapsed (the
+    device sources hold no string literals that contain comment markers)."""
+    data = re.sub(rb"/\*.*?\*/", b" ", data, flags=re.S)
+    data = re.sub(rb"//[^\n]*", b" ", data)
+    return re.sub(rb"\s+", b" ", data).strip()
+
+
 def kernel_hash() -> str:
     """Hash of the device code: the headers and the kernel source up to its
-    host-side section (host-only edits leave a traffic record valid; the launch
-    shape is checked separately)."""
+    host-side section, comments and layout ignored (host-only and comment
+    edits leave a traffic record valid; the launch shape is checked
+    separately)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1910_01972_amd", "csrc", f), "rb") as fh:
@@ -44,7 +54,7 @@ def kernel_hash() -> str:
             cut = data.find(HOST_MARKER)
             if cut >= 0:
                 data = data[:cut]
-        h.update(data)
+        h.update(_code_tokens(data))
     return h.hexdigest()[:16]
 
 

@@ -212,9 +212,10 @@ OLS_HD int granule_phase(const T* p) {
 // at the two ends of each chunk when the row is off the 64-byte grid) with
 // the default policy.  The first and last granule of a segment are partial
 // when they share a granule with the neighbouring segment; the chunk test
-// sees that exactly when the segment starts on a chunk boundary (D a
-// multiple of C), otherwise the head granule may go non-temporal, one
-// granule in H / LS.
+// sees that exactly when the segment's kept positions start and end on chunk
+// boundaries (D a multiple of C, and D + H = N as with the default hop),
+// otherwise its head and tail granules may go non-temporal, two granules in
+// H / LS.  The choice of policy never changes what is written.
 template <int N, int MODE, typename T, typename V>
 OLS_HD void store_segment(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H, int g, V val) {
   constexpr int LS = 64 / (int)sizeof(T);                // outputs per 64-byte granule
