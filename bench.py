@@ -234,7 +234,8 @@ def batched_measurement(steps: int, warmup: int) -> dict:
         return (time.perf_counter() - t0) * 1e3 / steps
 
     graph_ms = timed(graph.replay)
-    plans = [OLSPlan(h, N=b.item(i)["N"]) for i, (s, h, _) in enumerate(items)]
+    chosen = [b.item(i)["N"] for i in range(len(items))]
+    plans = [OLSPlan(h, N=chosen[i]) for i, (s, h, _) in enumerate(items)]
 
     def plain():
         for p, (s, h, _), y in zip(plans, items, b.outputs):
@@ -247,12 +248,40 @@ def batched_measurement(steps: int, warmup: int) -> dict:
         p.close()
     b.close()
     del graph
+
+    # The same batch with N per (M, K) from the autotuner (single-signal
+    # timings on a 2^22-sample proxy, N <= 4096), as its own captured graph.
+    from paper_1910_01972_amd import tuner
+    t0 = time.perf_counter()
+    g = torch.Generator(device="cuda").manual_seed(1)
+    proxy = torch.complex(torch.rand(1 << 22, device="cuda", generator=g) * 2 - 1,
+                          torch.rand(1 << 22, device="cuda", generator=g) * 2 - 1)
+    table = {}
+    for Ns, K, M, _ in shapes:
+        if (M, K) not in table:
+            h = torch.complex(torch.randn(K, M, device="cuda", generator=g),
+                              torch.randn(K, M, device="cuda", generator=g)) / M ** 0.5
+            table[(M, K)] = tuner.tune(M, K, reps=5, max_n=4096, data=(proxy, h), tile=False)["N"]
+    tune_s = time.perf_counter() - t0
+    bt = OLSBatch(items, fft_length=lambda M, K: table[(M, K)])
+    changed = sum(bt.item(i)["N"] != n for i, n in enumerate(chosen))
+    with torch.cuda.stream(stream):
+        bt.run(stream=stream)
+    stream.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        bt.run(stream=stream)
+    tuned_ms = timed(graph.replay)
+    bt.close()
+    del graph, proxy
     return {
         "workload": "uneven_batch_256", "signals": len(shapes), "output_samples": outputs,
-        "units": info["units"], "grid": info["grid"],
+        "units": info["units"], "grid": info["grid"], "fft_length": "library cost model",
         "graph_ms": graph_ms, "samples_per_s": outputs / (graph_ms * 1e-3),
         "GBps": alg / (graph_ms * 1e-3) / 1e9,
         "plain_per_signal_ms": plain_ms, "plain_samples_per_s": outputs / (plain_ms * 1e-3),
+        "tuned": {"fft_length": "autotuner, 2^22-sample proxy per (M, K)", "pairs": len(table),
+                  "tune_s": tune_s, "items_with_other_N": changed, "graph_ms": tuned_ms},
     }
 
 
