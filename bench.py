@@ -195,7 +195,7 @@ def variants_measurement(steps: int, warmup: int) -> dict:
     return out
 
 
-def batched_measurement(steps: int, warmup: int) -> dict:
+def batched_measurement(steps: int, warmup: int, tuned: bool = True) -> dict:
     """The uneven batch (256 signals, N_s log-uniform in [2^14, 2^22], K ~
     U{1..16}, M log-uniform in [16, 1024]) as ONE persistent launch captured in
     a hipGraph and replayed, beside the same items run as one plain launch per
@@ -248,6 +248,15 @@ def batched_measurement(steps: int, warmup: int) -> dict:
         p.close()
     b.close()
     del graph
+    rec = {
+        "workload": "uneven_batch_256", "signals": len(shapes), "output_samples": outputs,
+        "units": info["units"], "grid": info["grid"], "fft_length": "library cost model",
+        "graph_ms": graph_ms, "samples_per_s": outputs / (graph_ms * 1e-3),
+        "GBps": alg / (graph_ms * 1e-3) / 1e9,
+        "plain_per_signal_ms": plain_ms, "plain_samples_per_s": outputs / (plain_ms * 1e-3),
+    }
+    if not tuned:
+        return rec
 
     # The same batch with N per (M, K) from the autotuner (single-signal
     # timings on a 2^22-sample proxy, N <= 4096), as its own captured graph.
@@ -274,15 +283,9 @@ def batched_measurement(steps: int, warmup: int) -> dict:
     tuned_ms = timed(graph.replay)
     bt.close()
     del graph, proxy
-    return {
-        "workload": "uneven_batch_256", "signals": len(shapes), "output_samples": outputs,
-        "units": info["units"], "grid": info["grid"], "fft_length": "library cost model",
-        "graph_ms": graph_ms, "samples_per_s": outputs / (graph_ms * 1e-3),
-        "GBps": alg / (graph_ms * 1e-3) / 1e9,
-        "plain_per_signal_ms": plain_ms, "plain_samples_per_s": outputs / (plain_ms * 1e-3),
-        "tuned": {"fft_length": "autotuner, 2^22-sample proxy per (M, K)", "pairs": len(table),
-                  "tune_s": tune_s, "items_with_other_N": changed, "graph_ms": tuned_ms},
-    }
+    rec["tuned"] = {"fft_length": "autotuner, 2^22-sample proxy per (M, K)", "pairs": len(table),
+                    "tune_s": tune_s, "items_with_other_N": changed, "graph_ms": tuned_ms}
+    return rec
 
 
 def main():
@@ -294,6 +297,8 @@ def main():
     ap.add_argument("--no-side", action="store_true",
                     help="skip the side measurements (adjoint, batched, variants), so that a profile of this "
                          "run holds only the benchmark's launches")
+    ap.add_argument("--no-tuned-batch", action="store_true",
+                    help="skip the uneven batch with the autotuner's N (keeps a profile to one batch plan)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run the library's plain copy kernel on MIB MiB "
@@ -395,7 +400,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_side:
         rec["fwd_bwd"] = fwd_bwd_measurement(min(args.steps, 100), min(args.warmup, 50))
-        rec["batched"] = batched_measurement(max(3, min(args.steps, 200) // 20), 3)
+        rec["batched"] = batched_measurement(max(3, min(args.steps, 200) // 20), 3, tuned=not args.no_tuned_batch)
         rec["variants"] = variants_measurement(min(args.steps, 100), min(args.warmup, 50))
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(s_np, h_np, args.cpu_sample)
