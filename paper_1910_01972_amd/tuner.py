@@ -191,6 +191,21 @@ def sweep(reps: int = 10, tune_ns: int = 1 << 22):
         print(json.dumps(rec), flush=True)
 
 
+def run_config(M: int, K: int, Ns: int, N: int, nf: int, wpc: int, reps: int = 10) -> dict:
+    """The forward for one (M, K) on Ns synthetic samples with a fixed FFT
+    length and tiling: reps timed launches after two warm-ups."""
+    from .ols import OLSPlan
+    s, h = synthetic(Ns, K, M, seed=M * 1000 + K)
+    y = torch.empty((K, Ns), dtype=torch.complex64, device="cuda")
+    plan = OLSPlan(h, N=N)
+    plan.set_tiling(nf, wpc)
+    ms = _time_forward(plan, s, y, reps)
+    launch = plan.launch()
+    plan.close()
+    return {"M": M, "K": K, "Ns": Ns, "N": N, "filters_per_unit": nf, "workgroups_per_cu": wpc, "ms": ms,
+            "grid": launch["grid"]}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--M", type=int)
@@ -198,12 +213,17 @@ def main(argv=None):
     ap.add_argument("--Ns", type=int, default=1 << 22)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--run", nargs=3, type=int, metavar=("N", "NF", "WPC"),
+                    help="only run the forward for --M, --K on --Ns samples with this FFT length and tiling "
+                         "(filters per unit, workgroups per CU), e.g. under a profiler")
     a = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
         sys.path.insert(0, root)
     if a.sweep:
         sweep(reps=a.reps)
+    elif a.run:
+        print(json.dumps(run_config(a.M, a.K, a.Ns, *a.run, reps=a.reps)))
     else:
         print(json.dumps(tune(a.M, a.K, Ns=a.Ns, reps=a.reps)))
 
