@@ -246,8 +246,8 @@ def batched_measurement(steps: int, warmup: int, tuned: bool = True) -> dict:
     info = b.info()
     for p in plans:
         p.close()
+    del graph  # before the batch it replays is released
     b.close()
-    del graph
     rec = {
         "workload": "uneven_batch_256", "signals": len(shapes), "output_samples": outputs,
         "units": info["units"], "grid": info["grid"], "fft_length": "library cost model",
@@ -281,8 +281,8 @@ def batched_measurement(steps: int, warmup: int, tuned: bool = True) -> dict:
     with torch.cuda.graph(graph, stream=stream):
         bt.run(stream=stream)
     tuned_ms = timed(graph.replay)
-    bt.close()
     del graph, proxy
+    bt.close()
     rec["tuned"] = {"fft_length": "autotuner, 2^22-sample proxy per (M, K)", "pairs": len(table),
                     "tune_s": tune_s, "items_with_other_N": changed, "graph_ms": tuned_ms}
     return rec
