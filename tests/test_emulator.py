@@ -159,6 +159,25 @@ def test_batched_walk_vs_oracle():
             assert np.all(_rel(y, conv.direct_conv(it["s"], it["h"])) <= 1e-5)
 
 
+def test_batched_item_order_invariance():
+    """The plan deals tiles in class order (N, filters per unit) whatever the
+    caller's order: the same items in two orders give the same outputs,
+    bit for bit, for several grids."""
+    specs = [(4000, 2, 30, 512), (6000, 3, 200, 2048), (3000, 1, 20, 256), (5000, 4, 40, 256),
+             (7000, 5, 300, 1024), (2000, 2, 900, 4096), (4500, 6, 100, 512)]
+    items = []
+    for i, (Ns, K, M, N) in enumerate(specs):
+        s, h = workloads.make_signal_filters(Ns, K, M, seed=40 + i)
+        D = default_delay(N, M)
+        items.append(dict(s=s, h=h, N=N, D=D, H=N - D))
+    perm = [5, 2, 0, 6, 1, 4, 3]
+    for grid in (1, 7, 64):
+        a = emu.batched(items, grid)
+        b = emu.batched([items[j] for j in perm], grid)
+        for k, j in enumerate(perm):
+            assert np.array_equal(a[j], b[k])
+
+
 POST_CASES = [
     # (Ns, K, M, N, post): 1 derivative, 2 power, 3 power of the derivative
     (3000, 3, 40, 256, 1),

@@ -126,3 +126,13 @@ def test_batched_with_tuned_fft_lengths(ols, tmp_path):
         assert np.all(np.linalg.norm(y.cpu().numpy() - want, axis=1) <= 1e-5 * np.linalg.norm(want, axis=1))
     assert len(json.load(open(str(tmp_path / "tune.json")))) == 2  # one entry per distinct (M, K)
     b.close()
+
+
+def test_run_config_fixed_configuration(ols):
+    """tuner --run: the forward with a given N and tiling, timed; the launch
+    follows the tiling (workgroups per CU x CUs)."""
+    from paper_1910_01972_amd import tuner
+    r = tuner.run_config(100, 6, 1 << 18, 1024, 2, 1, reps=3)
+    assert r["N"] == 1024 and r["filters_per_unit"] == 2 and r["ms"] > 0
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert r["grid"] == cus
