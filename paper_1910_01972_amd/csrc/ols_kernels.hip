@@ -486,9 +486,12 @@ __global__ void ols_ds_fixup_kernel(const float2* __restrict__ ws_ds, float2* __
   // started in an earlier tile.  Hoisted out of the element loop (64-bit
   // divisions).
   const int64_t slot_lo = first_unit(U, P, blo) / K == t ? 0 : 1;
+  // blockIdx.y splits the window between workgroups: few outputs per lane,
+  // so the lanes' loads are all in flight at once
+  const int stride = blockDim.x * gridDim.y;
   for (int sg = 0; sg < GE::SEGS; ++sg) {
     const int64_t o0 = (t * GE::SEGS + sg) * H;
-    for (int p = threadIdx.x; p < H; p += blockDim.x) {
+    for (int p = threadIdx.x + blockIdx.y * blockDim.x; p < H; p += stride) {
       if (o0 + p >= Ns) break;
       float2 a = make_float2(0.f, 0.f);
       for (int64_t bb = blo; bb <= bhi; ++bb) {
@@ -670,8 +673,9 @@ struct Kern {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ds && grid > 1) {
-      hipLaunchKernelGGL(ols_ds_fixup_kernel<N>, dim3((unsigned)(grid - 1)), dim3(256), 0, st, p->ws_ds, ds, Ns, p->K,
-                         p->H, ntiles, grid);
+      // one workgroup per (tile boundary, eighth of the window): H <= 8192 outputs, at most 4 per lane
+      hipLaunchKernelGGL(ols_ds_fixup_kernel<N>, dim3((unsigned)(grid - 1), 8), dim3(256), 0, st, p->ws_ds, ds, Ns,
+                         p->K, p->H, ntiles, grid);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
