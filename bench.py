@@ -71,6 +71,31 @@ def measured_traffic(workload: str, launch: dict):
     return rec.get("hbm_bytes_per_launch")
 
 
+def launch_spread(ms) -> dict:
+    """Per-launch durations of the timed launches (HIP events): mean, min,
+    median, max, and the first and last launch."""
+    import numpy as np
+    ms = np.asarray(ms, dtype=np.float64)
+    return {"mean": float(ms.mean()), "min": float(ms.min()), "median": float(np.median(ms)),
+            "max": float(ms.max()), "first": float(ms[0]), "last": float(ms[-1]), "n": int(ms.size)}
+
+
+def settle_clocks(fn, settle_ms: float) -> dict:
+    """Runs fn back to back for settle_ms of wall time before any warm-up or
+    timed launch, so that the GPU leaves its idle power state first (from
+    idle, the first tens of milliseconds of launches run slower).  Reported
+    as its own field; none of these launches is timed."""
+    import torch
+    n = 0
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < settle_ms:
+        for _ in range(10):
+            fn()
+        n += 10
+        torch.cuda.synchronize()
+    return {"ms": (time.perf_counter() - t0) * 1e3, "launches": n}
+
+
 def cpu_baseline(s, h, n_sample: int):
     """The oracle (eq. 1 by definition, float64) on the first n_sample outputs
     of every filter row; returns samples/s and the BLAS thread count."""
@@ -300,6 +325,8 @@ def main():
     ap.add_argument("--no-tuned-batch", action="store_true",
                     help="skip the uneven batch with the autotuner's N (keeps a profile to one batch plan)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--settle-ms", type=float, default=1000.0,
+                    help="wall time of untimed back-to-back launches before the warm-up (reported as 'settle')")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run the library's plain copy kernel on MIB MiB "
                          "(known byte count, for scaling HBM traffic counters) and exit")
@@ -340,6 +367,7 @@ def main():
     launch_key = {"N": info["N"], "grid": launch["grid"], "block": launch["block"], "filters_per_unit": nf}
     stream = torch.cuda.current_stream()
 
+    settle = settle_clocks(lambda: plan.forward(s, y), args.settle_ms)
     for _ in range(args.warmup):
         plan.forward(s, y)
     torch.cuda.synchronize()
@@ -354,7 +382,8 @@ def main():
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(starts, ends)]))
+    launch_ms = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    kernel_ms = float(launch_ms.mean())
 
     ms_per_step = wall * 1e3 / args.steps
     outputs = wl.K * wl.Ns
@@ -392,8 +421,10 @@ def main():
             "traffic": traffic,
             "kernel": f"ols_forward_kernel<{info['N']}, {nf}, false, false>",
             "kernel_ms": kernel_ms,
+            "launch_ms": launch_spread(launch_ms),
             "alg_bytes_per_launch": alg_bytes,
         },
+        "settle": settle,
     }
     plan.close()
     del y

@@ -20,7 +20,12 @@
  *     anything, returns an ols_status_t and never throws or aborts; a failing
  *     call enqueues nothing; ols_last_error() gives a message for the calling
  *     thread's most recent failure;
- *   - index arithmetic is 64-bit (K * N_s may exceed 2^31).
+ *   - index arithmetic is 64-bit (K * N_s may exceed 2^31);
+ *   - a plan holds mutable device state -- its filter spectra (rewritten by
+ *     ols_plan_update_filters) and its backward workspace (rewritten by every
+ *     ols_backward) -- so the calls that use one plan must be ordered: enqueue
+ *     them on one stream, or order the streams with events.  Two plans never
+ *     share state.
  */
 #ifndef OLS_H_
 #define OLS_H_
@@ -199,31 +204,20 @@ ols_status_t ols_plan_reserve_backward(ols_plan_t plan);
 
 /*
  * Batched uneven overlap-and-save: many signals, each with its own filter bank
- * (K_i filters of length M_i) and FFT length, in ONE persistent kernel launch.
+ * (K_i filters of length M_i) and FFT length, in one persistent kernel launch
+ * (sec. 3.2 / Alg. 2 per item; the filter spectra first, Fig. 1).
  *
- * ols_batch_plan prepares the batch (the paper's plan step -- filter spectra
- * first, Fig. 1 / Alg. 2 -- for every item, the segment geometry of every
- * item, and the table of work units); ols_batched then enqueues a single
- * persistent kernel that processes every unit of every item (sec. 3.2 /
- * Alg. 2 per item) and allocates nothing, so it can be captured in a hipGraph
- * and replayed.  The batch keeps the item pointers: each replay reads the
- * signals and writes the outputs named at plan time.
- *
- * ols_batch_item_t (host array, copied):
+ * ols_batch_item_t, one per signal:
  *   s    device, complex64 [N_s];  N_s >= 0
- *   h    device, complex64 [K][M]; read during ols_batch_plan only
+ *   h    device, complex64 [K][M]
  *   K, M >= 1
  *   N    FFT length of this item: power of two in [256, 4096], or 0 for the
- *        library's choice (cost model; the Python tuner passes measured
- *        choices here)
+ *        library's choice (cost model: least transform work per kept sample)
  *   y    device, complex64 [K][N_s], must not overlap s; outputs of different
  *        items must not overlap each other (not checked)
- * Errors: INVALID_VALUE (item number in the message), UNSUPPORTED (N, or an
- * M needing N > 4096), OUT_OF_MEMORY, HIP.  ols_batch_plan synchronises
- * `stream` before returning.
+ * Pointers must be 8-byte aligned.
  */
 #define OLS_MAX_BATCH_FFT_LENGTH 4096
-typedef struct ols_batch_s* ols_batch_t;
 typedef struct {
   const void* s;
   int64_t N_s;
@@ -234,22 +228,74 @@ typedef struct {
   void* y;
 } ols_batch_item_t;
 
+/*
+ * ols_batched_workspace_size -- device bytes the workspace of ols_batched
+ * needs for these items (a header, twiddle tables, the ordered item table and
+ * the filter spectra, K x N complex64 per item at the FFT length it will
+ * use).  Host only: validates the items (HOST array, the same shapes the
+ * device array of ols_batched will hold) and touches no GPU.
+ * Errors: INVALID_VALUE (item number in the message), UNSUPPORTED (N, or an
+ * M needing N > 4096).
+ */
+ols_status_t ols_batched_workspace_size(const ols_batch_item_t* host_items, int32_t n_signals, size_t* bytes);
+
+/*
+ * ols_batched -- y_i = s_i * h_i,r for every item i and filter r (eq. 1, zero
+ * history), all items in one call.  Enqueues three kernels on `stream` and
+ * allocates nothing, so the call can be captured in a hipGraph and replayed:
+ *   1. setup (one workgroup): reads the DEVICE item array, repeats the item
+ *      checks, chooses each N, orders the items by (N, filters per unit) and
+ *      lays out the tile list and the spectra in the workspace;
+ *   2. the filter spectra of every item, FFT_N(pad h)/N, into the workspace
+ *      (so a replay sees the filters' current values);
+ *   3. one persistent forward kernel over the segment tiles of all items.
+ * Every replay reads dev_items again: the caller may change the items (new
+ * pointers, new filters, other shapes that fit the workspace) between calls.
+ *
+ *   dev_items  device, ols_batch_item_t [n_signals], 8-byte aligned
+ *   workspace  device, caller-owned, 256-byte aligned, ws_bytes long (at least
+ *              ols_batched_workspace_size of the same items); calls that
+ *              share a workspace must be ordered
+ * Errors on the host (nothing enqueued): INVALID_VALUE for NULL or misaligned
+ * pointers, n_signals < 1, or a workspace too small for n_signals items of
+ * the smallest size; HIP (launch).  Errors found on the device (an invalid
+ * item, or items that need more workspace than ws_bytes) make the call write
+ * no output at all; ols_batched_status reports them.
+ */
+ols_status_t ols_batched(const ols_batch_item_t* dev_items, int32_t n_signals, void* workspace, size_t ws_bytes,
+                         ols_stream_t stream);
+
+/*
+ * ols_batched_status -- outcome of the device-side checks of the last
+ * ols_batched call on `workspace`: *status = OLS_SUCCESS, INVALID_VALUE (an
+ * invalid item, or the workspace too small) or UNSUPPORTED (an item's N);
+ * *bad_item = the first invalid item's index, or -1.  Copies the workspace
+ * header back and synchronises `stream`.  Errors: INVALID_VALUE, HIP.
+ */
+ols_status_t ols_batched_status(const void* workspace, ols_stream_t stream, int32_t* status, int32_t* bad_item);
+
+/*
+ * Batch plans: the same batched computation with the setup and the filter
+ * spectra done once, at plan time, for repeated launches over fixed items.
+ * ols_batch_plan validates the HOST item array, allocates the batch's own
+ * workspace, runs the setup and spectra kernels of ols_batched on `stream`
+ * and synchronises it; ols_batch_run then enqueues only the persistent
+ * forward kernel (allocates nothing; capturable).  The batch keeps the item
+ * pointers: each run reads the signals and writes the outputs named at plan
+ * time, with the filter spectra of plan time.
+ * Errors: as ols_batched_workspace_size, OUT_OF_MEMORY, HIP.
+ */
+typedef struct ols_batch_s* ols_batch_t;
 ols_status_t ols_batch_plan(ols_batch_t* batch, const ols_batch_item_t* items, int32_t n, ols_stream_t stream);
 
-/* Device bytes that ols_batch_plan allocates for these items (filter spectra
- * K x N complex64 per item at the FFT length it would choose, the item table
- * and the twiddle tables), without allocating anything; items are validated
- * as by ols_batch_plan.  Errors: as ols_batch_plan (host checks only). */
-ols_status_t ols_batched_workspace_size(const ols_batch_item_t* items, int32_t n, size_t* bytes);
-
-/* One persistent launch over all items of the batch, on `stream`.
+/* One persistent launch over all items of a batch plan, on `stream`.
  * Allocates nothing; capturable.  Errors: INVALID_VALUE, HIP. */
-ols_status_t ols_batched(ols_batch_t batch, ols_stream_t stream);
+ols_status_t ols_batch_run(ols_batch_t batch, ols_stream_t stream);
 
 /* Total work units, launch grid and item count of a batch (NULL outputs skipped). */
 ols_status_t ols_batch_get_info(ols_batch_t batch, int64_t* total_units, int32_t* grid, int32_t* n);
 
-/* FFT length, hop and delay chosen for item i. */
+/* FFT length, hop and delay chosen for item i (the caller's numbering). */
 ols_status_t ols_batch_get_item(ols_batch_t batch, int32_t i, int32_t* N, int32_t* H, int32_t* D);
 
 /* Release a batch (NULL is a no-op). */

@@ -47,7 +47,9 @@ SIGNATURES = {
     "ols_backward": (_I32, [_P, _P, _I64, _P, _P, _P, _P]),
     "ols_plan_reserve_backward": (_I32, [_P]),
     "ols_batch_plan": (_I32, [ctypes.POINTER(_P), _P, _I32, _P]),
-    "ols_batched": (_I32, [_P, _P]),
+    "ols_batch_run": (_I32, [_P, _P]),
+    "ols_batched": (_I32, [_P, _I32, _P, ctypes.c_size_t, _P]),
+    "ols_batched_status": (_I32, [_P, _P, _PI32, _PI32]),
     "ols_batch_get_info": (_I32, [_P, ctypes.POINTER(_I64), _PI32, _PI32]),
     "ols_batch_get_item": (_I32, [_P, _I32, _PI32, _PI32, _PI32]),
     "ols_batch_destroy": (_I32, [_P]),

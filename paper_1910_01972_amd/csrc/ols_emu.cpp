@@ -632,6 +632,10 @@ int ols_emu_spectra(int N, const float* h, int K, int M, float* out) {
 // size (float2), out[7] twiddle table size.
 int ols_emu_lds_report(int N, int64_t* out) { return ols::emu::dispatch<ols::emu::RunLds>(N, out); }
 
+// The library's FFT-length cost model (exact integer comparison) for K
+// filters of M taps and lengths up to max_n; 0 if none fits.
+int ols_emu_cost_model(int K, int M, int max_n) { return ols::cost_model_fft_length(K, M, max_n); }
+
 // out[0..6] = G, P, R0, WG, SEGS, LDS (float2), TWR
 int ols_emu_geometry(int N, int32_t* out) { return ols::emu::dispatch<ols::emu::RunGeo>(N, out); }
 

@@ -129,16 +129,16 @@ __device__ __forceinline__ void inverse_of_products(float2 (&x)[NF][16], const f
 // Filter spectra (plan step): F_r = FFT_N(pad(h_r)) / N in kernel order;
 // h is complex64, or float32 for R2R plans (real != 0).
 // ---------------------------------------------------------------------------
+// Filters r0 .. r0 + SEGS - 1 (those < K) of one filter bank, one transform
+// per G lanes; the body of the plan step and of the batch setup.
 template <int N>
-__global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const void* __restrict__ h, int K, int M,
-                                                                        float2* __restrict__ F,
-                                                                        const float2* __restrict__ twt, int diff,
-                                                                        int real) {
+__device__ __forceinline__ void filter_spectra_block(const void* __restrict__ h, int K, int M, float2* __restrict__ F,
+                                                     const float2* __restrict__ twt, int diff, int real, int r0,
+                                                     float2* lds) {
   using GE = Geo<N>;
-  __shared__ float2 lds[2 * GE::LDS];
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
-  const int r = blockIdx.x * GE::SEGS + grp;
+  const int r = r0 + grp;
   int par = 0;
   float2 tw[GE::TWR];
   load_lane_twiddles<N>(tw, twt, g);
@@ -150,6 +150,15 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const vo
   else load_filter<N>(x, (const float2*)h + row, M, valid, g);
   fwd_from<N, 0>(x, lds, par, tw, grp, g);
   if (valid) store_spectrum<N>(x, F, r, g, 1.0f / (float)N);
+}
+
+template <int N>
+__global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const void* __restrict__ h, int K, int M,
+                                                                        float2* __restrict__ F,
+                                                                        const float2* __restrict__ twt, int diff,
+                                                                        int real) {
+  __shared__ float2 lds[2 * Geo<N>::LDS];
+  filter_spectra_block<N>(h, K, M, F, twt, diff, real, blockIdx.x * Geo<N>::SEGS, lds);
 }
 
 // Natural-order copy of the spectra: out[r][k] = F[r][spectrum_offset(reg, g)]
@@ -178,7 +187,22 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
 // (real part 2q, imaginary part 2q+1), so a tile is SEGS pairs.  POWER
 // stores |y|^2 (float32) instead of y.
 // tw: this lane's twiddles (load_lane_twiddles).
-template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE>
+// Spectrum prefetch (PF).  Vector-memory loads and stores share one in-order
+// completion counter, so a load issued after a unit's output stores can only
+// be waited for once those stores have been acknowledged as well: with the
+// spectra loaded at the start of each unit, every unit waits until the
+// previous unit's stores have drained.  With PF the spectra of unit u+1 are
+// loaded right after unit u's inverse transforms and BEFORE its stores, into a
+// second register set; the two sets swap roles from one unit to the next (the
+// loop is unrolled by two so that no register copy is needed).  It costs a
+// second set of spectrum registers: with one filter per unit it measured
+// 2-7 % faster (N = 512, 2048, 4096, 8192; 2-3 % slower at N = 1024), with
+// two filters per unit the extra 64 registers halve the occupancy.
+template <int N, int NF>
+constexpr bool prefetch_spectra() { return NF == 1 && N != 1024; }
+
+template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE,
+          bool PF = prefetch_spectra<N, NF>()>
 __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2 (&tw)[Geo<N>::TWR], int64_t u0, int64_t u1, float2* lds,
@@ -191,7 +215,7 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
 
   int64_t tile = u0 / KG;
   int rg = (int)(u0 - tile * KG);
-  float2 A[16], x[NF][16];
+  float2 A[16], xa[NF][16], xb[NF][16];
 
   // Transform index of this lane (a segment, or a segment pair for REAL);
   // uniform over a wave when a transform spans whole waves (G >= 64).
@@ -199,48 +223,76 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
     const int64_t sg = t * GE::SEGS + grp;
     return GE::G >= 64 ? wave_uniform64(sg) : sg;
   };
-  auto load = [&](int64_t sg) {
-    if constexpr (REAL) load_segment_pair<N>(x[0], (const float*)sv, Ns, sg * step - D, H, g);
-    else load_segment<N>(x[0], (const float2*)sv, Ns, sg * step - D, g);
+  // segment (pair) sg, forward transformed, into A (x is scratch)
+  auto transform_segment = [&](float2 (&x)[16], int64_t sg) {
+    if constexpr (REAL) load_segment_pair<N>(x, (const float*)sv, Ns, sg * step - D, H, g);
+    else load_segment<N>(x, (const float2*)sv, Ns, sg * step - D, g);
+    fwd_from<N, 0>(x, lds, par, tw, grp, g);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) A[i] = x[i];
+  };
+  // spectra of filter group q; filters past K (a ragged last group) reuse the
+  // last filter's spectrum and are not stored
+  auto load_group = [&](float2 (&x)[NF][16], int q) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int r = q * NF + f;
+      load_spectrum<N>(x[f], F, r < K ? r : K - 1, g);
+    }
+  };
+  auto store_group = [&](const float2 (&x)[NF][16], int q, int64_t sg) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int r = q * NF + f;
+      if (NF == 1 || r < K) {
+        if constexpr (REAL)
+          store_valid_pair<N, POWER, SMODE>(x[f], (float*)yv + (int64_t)r * Ns, Ns, sg * step, D, H, g);
+        else if constexpr (POWER)
+          store_valid_power<N, SMODE>(x[f], (float*)yv + (int64_t)r * Ns, Ns, sg * step, D, H, g);
+        else
+          store_valid<N, SMODE>(x[f], (float2*)yv + (int64_t)r * Ns, Ns, sg * step, D, H, g);
+      }
+    }
   };
 
   int64_t seg = segment_of(tile);
-  load(seg);
-  fwd_from<N, 0>(x[0], lds, par, tw, grp, g);
-#pragma unroll
-  for (int i = 0; i < 16; ++i) A[i] = x[0][i];
-
-  for (int64_t u = u0; u < u1; ++u) {
-    if (rg == KG) {  // next tile: new segments, one forward transform each
-      rg = 0;
-      ++tile;
-      seg = segment_of(tile);
-      load(seg);
-      fwd_from<N, 0>(x[0], lds, par, tw, grp, g);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) A[i] = x[0][i];
-    }
-    // spectra of this unit's filters; filters past K (a ragged last group)
-    // reuse the last filter's spectrum and are not stored
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int r = rg * NF + f;
-      load_spectrum<N>(x[f], F, r < K ? r : K - 1, g);
-    }
-    inverse_of_products<N, NF>(x, A, lds, par, tw, grp, g);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int r = rg * NF + f;
-      if (NF == 1 || r < K) {
-        if constexpr (REAL)
-          store_valid_pair<N, POWER, SMODE>(x[f], (float*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
-        else if constexpr (POWER)
-          store_valid_power<N, SMODE>(x[f], (float*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
-        else
-          store_valid<N, SMODE>(x[f], (float2*)yv + (int64_t)r * Ns, Ns, seg * step, D, H, g);
+  if constexpr (PF) {
+    load_group(xa, rg);
+    transform_segment(xb[0], seg);
+    // cur holds unit u's spectra on entry; nxt is free and receives unit u+1's
+    auto unit = [&](float2 (&cur)[NF][16], float2 (&nxt)[NF][16], int64_t u) {
+      if (rg == KG) {  // next tile: new segments, one forward transform each
+        rg = 0;
+        ++tile;
+        seg = segment_of(tile);
+        transform_segment(nxt[0], seg);
       }
+      inverse_of_products<N, NF>(cur, A, lds, par, tw, grp, g);
+      if (u + 1 < u1) load_group(nxt, rg + 1 == KG ? 0 : rg + 1);
+      __builtin_amdgcn_sched_barrier(0);  // keep those loads ahead of the stores
+      store_group(cur, rg, seg);
+      ++rg;
+    };
+    int64_t u = u0;
+    for (; u + 1 < u1; u += 2) {
+      unit(xa, xb, u);
+      unit(xb, xa, u + 1);
     }
-    ++rg;
+    if (u < u1) unit(xa, xb, u);
+  } else {
+    transform_segment(xa[0], seg);
+    for (int64_t u = u0; u < u1; ++u) {
+      if (rg == KG) {
+        rg = 0;
+        ++tile;
+        seg = segment_of(tile);
+        transform_segment(xa[0], seg);
+      }
+      load_group(xa, rg);
+      inverse_of_products<N, NF>(xa, A, lds, par, tw, grp, g);
+      store_group(xa, rg, seg);
+      ++rg;
+    }
   }
 }
 
@@ -284,6 +336,7 @@ struct BatchItem {
   const float2* s;
   float2* y;
   const float2* spectra;  // [K][N] in transform order, scaled by 1/N
+  const void* h;          // the caller's filters [K][M] (read by the spectra step)
   int64_t Ns;
   int64_t unit_begin;
   int64_t units;
@@ -292,6 +345,273 @@ struct BatchItem {
   int64_t ntiles;      // tiles of this item (units = ntiles * units per tile)
 };
 
+// Values the batch setup computes on the device: totals over all items and
+// the outcome of its checks.  Every later kernel of a batched call reads
+// status first and does nothing unless it is OLS_SUCCESS.
+struct BatchHeader {
+  int32_t status;       // ols_status_t of the device-side checks
+  int32_t bad_item;     // first failing item (caller's numbering), -1 if none
+  int32_t n;
+  int32_t pad;
+  int64_t total_tiles;  // segment tiles of all items
+  int64_t total_tasks;  // spectrum tasks (one workgroup's filters of one item)
+  int64_t spec_elems;   // complex64 elements of filter spectra the items need
+};
+
+// Where each part of a batch's device state lives: in the caller's
+// workspace (ols_batched) or in a batch plan's own allocation.  Passed to
+// every batch kernel by value.
+constexpr int BATCH_LENGTHS = 5;  // N = 256, 512, 1024, 2048, 4096
+struct BatchLayout {
+  BatchHeader* hdr;
+  BatchItem* items;     // [n], in kernel order (by class, stable)
+  int64_t* task_begin;  // [n + 1], first spectrum task of each item (kernel order)
+  int32_t* order;       // [n], caller's index of each kernel-order item
+  float2* tw[BATCH_LENGTHS];
+  float2* spectra;
+  int64_t spec_capacity;  // complex64 elements available at `spectra`
+  int32_t n;
+};
+
+// ---------------------------------------------------------------------------
+// Batch setup: one workgroup reads the caller's items (a device array),
+// checks them, chooses each item's FFT length, orders the items by class
+// (N, filters per unit) -- a stable counting sort -- and lays out the tile
+// list, the spectrum tasks and the spectra with prefix sums.  It also writes
+// the twiddle tables of the five batched lengths, evaluated in float64 from
+// the exact reduced angle and rounded once to float32.
+// ---------------------------------------------------------------------------
+constexpr int SETUP_THREADS = 1024;
+
+// Exclusive prefix sum over the workgroup of one value per thread; *total
+// receives the sum over all threads.  sh holds SETUP_THREADS values.
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < SETUP_THREADS; off <<= 1) {
+    const int64_t a = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  const int64_t incl = sh[t];
+  *total = sh[SETUP_THREADS - 1];
+  __syncthreads();  // sh is reused by the next scan
+  return incl - v;
+}
+
+template <int N>
+__device__ void device_twiddles(float2* __restrict__ out) {
+  using GE = Geo<N>;
+#pragma unroll
+  for (int k = 0; k < GE::P - 1; ++k) {
+    const int L = GE::len(k), S = GE::strd(k), cnt = GE::tw_count(k);
+    for (int idx = threadIdx.x; idx < cnt; idx += SETUP_THREADS) {
+      const int b = idx / S + 1, l = idx - (b - 1) * S;
+      const int m = (int)(((int64_t)l * b) % L);
+      double sn, cs;
+      sincospi(2.0 * (double)m / (double)L, &sn, &cs);  // exp(-2 pi i m / L) = cos - i sin
+      out[GE::tw_offset(k) + idx] = make_float2((float)cs, (float)(-sn));
+    }
+  }
+}
+
+struct ItemShape {
+  int N, nf, cls;
+  int64_t ntiles, units, spec, tasks;
+};
+
+__device__ __forceinline__ ItemShape item_shape(const ols_batch_item_t& it, int N) {
+  ItemShape r;
+  r.N = N;
+  r.nf = choose_nf_batched(N, it.K);
+  r.cls = batch_class(N, r.nf);
+  const int H = N - default_delay(N, it.M);
+  const int segs = 4096 / N;  // transforms per 256-thread workgroup
+  const int64_t nseg = (it.N_s + H - 1) / H;
+  r.ntiles = (nseg + segs - 1) / segs;
+  r.units = r.ntiles * ((it.K + r.nf - 1) / r.nf);
+  r.spec = (int64_t)it.K * N;
+  r.tasks = (it.K + segs - 1) / segs;
+  return r;
+}
+
+__global__ __launch_bounds__(SETUP_THREADS) void ols_batch_setup_kernel(const ols_batch_item_t* __restrict__ in,
+                                                                         BatchLayout L) {
+  __shared__ int cnt[BATCH_CLASSES][SETUP_THREADS];
+  __shared__ int64_t sh[SETUP_THREADS];
+  __shared__ int64_t cls_total[BATCH_CLASSES];
+  __shared__ unsigned long long s_fail;
+  const int t = threadIdx.x, n = L.n;
+  const int chunk = (n + SETUP_THREADS - 1) / SETUP_THREADS;
+  const int i0 = t * chunk < n ? t * chunk : n;
+  const int i1 = i0 + chunk < n ? i0 + chunk : n;
+  if (t == 0) s_fail = ~0ull;
+  __syncthreads();
+
+  // 1. check every item, count the items of each class in this thread's chunk
+  int local[BATCH_CLASSES];
+#pragma unroll
+  for (int c = 0; c < BATCH_CLASSES; ++c) local[c] = 0;
+  for (int i = i0; i < i1; ++i) {
+    const ols_batch_item_t it = in[i];
+    int N = 0;
+    const int st = batch_item_check(it.s, it.N_s, it.h, it.K, it.M, it.N, it.y, &N);
+    if (st != 0) {
+      atomicMin(&s_fail, ((unsigned long long)i << 8) | (unsigned)st);
+      continue;
+    }
+    ++local[batch_class(N, choose_nf_batched(N, it.K))];
+  }
+  __syncthreads();
+  if (s_fail != ~0ull) {  // uniform: no item is processed
+    if (t == 0) {
+      L.hdr->status = (int32_t)(s_fail & 0xff);
+      L.hdr->bad_item = (int32_t)(s_fail >> 8);
+      L.hdr->n = n;
+      L.hdr->total_tiles = 0;
+      L.hdr->total_tasks = 0;
+      L.hdr->spec_elems = 0;
+    }
+    return;
+  }
+
+  // 2. stable counting sort by class: exclusive prefix of every class's
+  // counts over the threads, then class bases
+#pragma unroll
+  for (int c = 0; c < BATCH_CLASSES; ++c) {
+    int64_t tot;
+    cnt[c][t] = (int)block_exclusive_scan(local[c], sh, &tot);
+    if (t == 0) cls_total[c] = tot;
+  }
+  __syncthreads();
+  int64_t base[BATCH_CLASSES];
+  {
+    int64_t acc = 0;
+#pragma unroll
+    for (int c = 0; c < BATCH_CLASSES; ++c) {
+      base[c] = acc + cnt[c][t];
+      acc += cls_total[c];
+    }
+  }
+  for (int i = i0; i < i1; ++i) {
+    const ols_batch_item_t it = in[i];
+    int N = 0;
+    (void)batch_item_check(it.s, it.N_s, it.h, it.K, it.M, it.N, it.y, &N);
+    const ItemShape sh_ = item_shape(it, N);
+    const int64_t pos = base[sh_.cls]++;
+    BatchItem b;
+    b.s = (const float2*)it.s;
+    b.y = (float2*)it.y;
+    b.spectra = nullptr;
+    b.h = it.h;
+    b.Ns = it.N_s;
+    b.unit_begin = 0;
+    b.units = sh_.units;
+    b.K = it.K;
+    b.M = it.M;
+    b.N = N;
+    b.D = default_delay(N, it.M);
+    b.H = N - b.D;
+    b.nf = sh_.nf;
+    b.tile_begin = 0;
+    b.ntiles = sh_.ntiles;
+    L.items[pos] = b;
+    L.order[pos] = i;
+  }
+  __syncthreads();  // the sorted table is complete (workgroup-scope visibility of global writes)
+
+  // 3. prefix sums in kernel order: tiles, units, spectra, spectrum tasks
+  int64_t my_tiles = 0, my_units = 0, my_spec = 0, my_tasks = 0;
+  for (int p = i0; p < i1; ++p) {
+    const BatchItem& b = L.items[p];
+    my_tiles += b.ntiles;
+    my_units += b.units;
+    my_spec += (int64_t)b.K * b.N;
+    my_tasks += (b.K + 4096 / b.N - 1) / (4096 / b.N);
+  }
+  int64_t tot_tiles, tot_units, tot_spec, tot_tasks;
+  int64_t o_tiles = block_exclusive_scan(my_tiles, sh, &tot_tiles);
+  int64_t o_units = block_exclusive_scan(my_units, sh, &tot_units);
+  int64_t o_spec = block_exclusive_scan(my_spec, sh, &tot_spec);
+  int64_t o_tasks = block_exclusive_scan(my_tasks, sh, &tot_tasks);
+  const bool fits = tot_spec <= L.spec_capacity;
+  for (int p = i0; p < i1; ++p) {
+    BatchItem& b = L.items[p];
+    b.tile_begin = o_tiles;
+    b.unit_begin = o_units;
+    b.spectra = fits ? L.spectra + o_spec : nullptr;
+    L.task_begin[p] = o_tasks;
+    o_tiles += b.ntiles;
+    o_units += b.units;
+    o_spec += (int64_t)b.K * b.N;
+    o_tasks += (b.K + 4096 / b.N - 1) / (4096 / b.N);
+  }
+  if (t == 0) {
+    L.task_begin[n] = tot_tasks;
+    L.hdr->status = fits ? 0 : (int32_t)OLS_ERROR_INVALID_VALUE;
+    L.hdr->bad_item = -1;
+    L.hdr->n = n;
+    L.hdr->total_tiles = tot_tiles;
+    L.hdr->total_tasks = tot_tasks;
+    L.hdr->spec_elems = tot_spec;
+  }
+
+  // 4. twiddle tables
+  device_twiddles<256>(L.tw[0]);
+  device_twiddles<512>(L.tw[1]);
+  device_twiddles<1024>(L.tw[2]);
+  device_twiddles<2048>(L.tw[3]);
+  device_twiddles<4096>(L.tw[4]);
+}
+
+// One length's spectrum body as its own function, so the kernel's register
+// count is the largest body's rather than the sum of all five.
+template <int N>
+__device__ __attribute__((noinline)) void batch_spectra_task(const BatchItem& it, const float2* __restrict__ twt,
+                                                              int r0, float2* lds) {
+  filter_spectra_block<N>(it.h, it.K, it.M, (float2*)it.spectra, twt, 0, 0, r0, lds);
+}
+
+// Filter spectra of every item: task tau is one workgroup's filters of one
+// item (SEGS = 4096 / N of them); persistent workgroups take tasks b, b + P, ...
+__global__ __launch_bounds__(256) void ols_batch_spectra_kernel(BatchLayout L) {
+  __shared__ float2 lds[2 * Geo<4096>::LDS];
+  if (L.hdr->status != 0) return;
+  const int64_t tasks = L.hdr->total_tasks;
+  for (int64_t tau = blockIdx.x; tau < tasks; tau += gridDim.x) {
+    // the item whose task range holds tau: task_begin[i] <= tau < task_begin[i + 1]
+    int lo = 0, hi = L.n;  // invariant: task_begin[lo] <= tau < task_begin[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (L.task_begin[mid] <= tau) lo = mid;
+      else hi = mid;
+    }
+    const BatchItem& it = L.items[lo];
+    const int r0 = (int)(tau - L.task_begin[lo]) * (4096 / it.N);
+    __syncthreads();  // the previous task's transform may still read LDS
+    switch (it.N) {
+      case 256: batch_spectra_task<256>(it, L.tw[0], r0, lds); break;
+      case 512: batch_spectra_task<512>(it, L.tw[1], r0, lds); break;
+      case 1024: batch_spectra_task<1024>(it, L.tw[2], r0, lds); break;
+      case 2048: batch_spectra_task<2048>(it, L.tw[3], r0, lds); break;
+      default: batch_spectra_task<4096>(it, L.tw[4], r0, lds); break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched forward: many signals, each with its own filters (K_i, M_i), FFT
+// length N_i in {256, ..., 4096} and hop, in one persistent launch.  The
+// items' segment tiles are numbered consecutively (item i owns tiles
+// [tile_begin_i, tile_begin_i + ntiles_i)) and dealt round-robin to the
+// workgroups; for each tile a workgroup switches on its item's (N, filters
+// per unit) to the same range body as the single-signal kernel, over all of
+// the tile's units.  Every N <= 4096 uses 256 threads and the same LDS
+// footprint, so one launch covers them all.
+// ---------------------------------------------------------------------------
+
 // Each (N, filters per unit) body is its own non-inlined function, so its
 // registers are allocated on their own and the kernel needs only the
 // maximum, not the sum, over the branches it may take.  A body runs the
@@ -299,8 +619,8 @@ struct BatchItem {
 // (N, filters per unit): the lane twiddles are loaded once per run, and
 // consecutive tiles of one class need no barrier between them (the same
 // exchange protocol as consecutive tiles of the single-signal kernel).  The
-// batch plan orders the items by class, so a workgroup meets each class in
-// one run.  Returns the workgroup's first tile of another class (or past the
+// setup orders the items by class, so a workgroup meets each class in one
+// run.  Returns the workgroup's first tile of another class (or past the
 // end); i follows the item walk.
 template <int N, int NF>
 __device__ __attribute__((noinline)) int64_t batched_run(const BatchItem* __restrict__ items, int nitems, int& i,
@@ -312,8 +632,8 @@ __device__ __attribute__((noinline)) int64_t batched_run(const BatchItem* __rest
     const BatchItem& it = items[i];
     const int64_t per_tile = it.units / it.ntiles;
     const int64_t a = (t - it.tile_begin) * per_tile;
-    forward_units<N, NF, false, false, STORE_NT>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a,
-                                                  a + per_tile, lds, par);
+    forward_units<N, NF, false, false, STORE_NT, false>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a,
+                                                        a + per_tile, lds, par);
     t += gridDim.x;
     if (t >= total_tiles) return t;
     // t grows, so the item walk only moves forward (items without tiles are skipped)
@@ -336,15 +656,14 @@ __device__ __forceinline__ int64_t batched_class(const BatchItem* __restrict__ i
   return batched_run<N, 1>(items, nitems, i, t, total_tiles, twt, lds, par);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ols_batched_kernel(const BatchItem* __restrict__ items, int nitems,
-                                                          int64_t total_tiles, const float2* __restrict__ tw256,
-                                                          const float2* __restrict__ tw512,
-                                                          const float2* __restrict__ tw1024,
-                                                          const float2* __restrict__ tw2048,
-                                                          const float2* __restrict__ tw4096) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ols_batched_kernel(BatchLayout L) {
   __shared__ float2 lds[2 * Geo<4096>::LDS];
   static_assert(Geo<256>::LDS == Geo<4096>::LDS && Geo<2048>::LDS == Geo<4096>::LDS, "same LDS footprint");
-  // Tiles of all items, in the plan's item order, dealt round-robin to the
+  if (L.hdr->status != 0) return;
+  const int64_t total_tiles = L.hdr->total_tiles;
+  const BatchItem* __restrict__ items = L.items;
+  const int nitems = L.n;
+  // Tiles of all items, in the setup's item order, dealt round-robin to the
   // workgroups: workgroup b takes tiles b, b + P, b + 2P, ... with all of
   // each tile's filters.  At any moment the whole grid works on neighbouring
   // tiles of one or two items, so every XCD keeps those items' filter
@@ -361,11 +680,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void o
     // finished with the previous run's buffers
     __syncthreads();
     switch (items[i].N) {
-      case 256: t = batched_class<256>(items, nitems, i, t, total_tiles, tw256, lds, par); break;
-      case 512: t = batched_class<512>(items, nitems, i, t, total_tiles, tw512, lds, par); break;
-      case 1024: t = batched_class<1024>(items, nitems, i, t, total_tiles, tw1024, lds, par); break;
-      case 2048: t = batched_class<2048>(items, nitems, i, t, total_tiles, tw2048, lds, par); break;
-      default: t = batched_class<4096>(items, nitems, i, t, total_tiles, tw4096, lds, par); break;
+      case 256: t = batched_class<256>(items, nitems, i, t, total_tiles, L.tw[0], lds, par); break;
+      case 512: t = batched_class<512>(items, nitems, i, t, total_tiles, L.tw[1], lds, par); break;
+      case 1024: t = batched_class<1024>(items, nitems, i, t, total_tiles, L.tw[2], lds, par); break;
+      case 2048: t = batched_class<2048>(items, nitems, i, t, total_tiles, L.tw[3], lds, par); break;
+      default: t = batched_class<4096>(items, nitems, i, t, total_tiles, L.tw[4], lds, par); break;
     }
   }
 }
@@ -565,15 +884,14 @@ struct ols_plan_s {
 
 struct ols_batch_s {
   int n = 0;
+  int grid = 0;         // persistent workgroups of the batched kernel
+  void* ws = nullptr;   // the batch's own workspace (same layout as ols_batched's)
+  ols_batch_item_t* dev_items = nullptr;
+  BatchLayout L{};
+  std::vector<BatchItem> items_sorted;  // kernel order (copied back after the setup)
+  std::vector<int32_t> order;           // caller's index of each kernel-order item
+  std::vector<int32_t> pos_of;          // kernel position of each caller item
   int64_t total_units = 0;
-  int grid = 0;
-  int cus = 0;
-  BatchItem* items_dev = nullptr;       // in kernel order (items_sorted)
-  std::vector<BatchItem> items_host;    // in the caller's order
-  std::vector<BatchItem> items_sorted;  // by class (N, filters per unit)
-  std::vector<int> order;               // items_sorted[k] = items_host[order[k]]
-  float2* spectra = nullptr;
-  float2* tw[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // N = 256 .. 4096
   int64_t total_tiles = 0;
 };
 
@@ -591,23 +909,6 @@ ols_status_t hip_fail(hipError_t e, const char* what) {
 }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
-
-int default_delay(int N, int M) {
-  const int d = ((M - 1) + 15) / 16 * 16;
-  return d <= N - 1 ? d : M - 1;
-}
-
-// Approximate FFT work per valid output sample for FFT length N; used when
-// the caller passes N = 0.
-double cost_per_output(int N, int M, int K) {
-  const int D = default_delay(N, M);
-  const int H = N - D;
-  if (H < 1) return 1e300;
-  const double lg = std::log2((double)N);
-  const double per_fft = 3.2 * N * lg;
-  const double work = (K + 1.0) * per_fft + K * 4.0 * N;
-  return work / ((double)K * H);
-}
 
 
 template <int N>
@@ -751,11 +1052,82 @@ struct RunShape {
 
 void destroy_batch(ols_batch_s* b) {
   if (!b) return;
-  if (b->items_dev) (void)hipFree(b->items_dev);
-  if (b->spectra) (void)hipFree(b->spectra);
-  for (auto* t : b->tw)
-    if (t) (void)hipFree(t);
+  if (b->ws) (void)hipFree(b->ws);
+  if (b->dev_items) (void)hipFree(b->dev_items);
   delete b;
+}
+
+// Layout of a batch workspace for n items: header, the five twiddle tables,
+// the kernel-order item table, spectrum-task offsets, the caller order, then
+// the filter spectra; every part starts on a 256-byte boundary.
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr int BATCH_TW_ELEMS[BATCH_LENGTHS] = {Geo<256>::TW_TOTAL, Geo<512>::TW_TOTAL, Geo<1024>::TW_TOTAL,
+                                               Geo<2048>::TW_TOTAL, Geo<4096>::TW_TOTAL};
+struct BatchOffsets {
+  size_t hdr, tw[BATCH_LENGTHS], items, task, order, spec;
+};
+BatchOffsets batch_offsets(int n) {
+  BatchOffsets o{};
+  size_t off = 0;
+  o.hdr = off;
+  off = align256(off + sizeof(BatchHeader));
+  for (int k = 0; k < BATCH_LENGTHS; ++k) {
+    o.tw[k] = off;
+    off = align256(off + (size_t)BATCH_TW_ELEMS[k] * sizeof(float2));
+  }
+  o.items = off;
+  off = align256(off + (size_t)n * sizeof(BatchItem));
+  o.task = off;
+  off = align256(off + (size_t)(n + 1) * sizeof(int64_t));
+  o.order = off;
+  off = align256(off + (size_t)n * sizeof(int32_t));
+  o.spec = off;
+  return o;
+}
+BatchLayout batch_layout(void* ws, size_t bytes, int n) {
+  const BatchOffsets o = batch_offsets(n);
+  char* base = (char*)ws;
+  BatchLayout L{};
+  L.hdr = (BatchHeader*)(base + o.hdr);
+  for (int k = 0; k < BATCH_LENGTHS; ++k) L.tw[k] = (float2*)(base + o.tw[k]);
+  L.items = (BatchItem*)(base + o.items);
+  L.task_begin = (int64_t*)(base + o.task);
+  L.order = (int32_t*)(base + o.order);
+  L.spectra = (float2*)(base + o.spec);
+  L.spec_capacity = bytes > o.spec ? (int64_t)((bytes - o.spec) / sizeof(float2)) : 0;
+  L.n = n;
+  return L;
+}
+
+// Persistent grids of the batch kernels on the current device.
+hipError_t batch_grids(int* batched, int* spectra) {
+  int dev = 0, cus = 0, a = 0, b = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, ols_batched_kernel, 256, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, ols_batch_spectra_kernel, 256, 0);
+  *batched = (a < 1 ? 1 : a) * cus;
+  *spectra = (b < 1 ? 1 : b) * cus;
+  return e;
+}
+
+// The three launches of a batched call: setup, filter spectra, the persistent
+// forward.  Allocate nothing; capturable.
+hipError_t launch_batch(const ols_batch_item_t* dev_items, const BatchLayout& L, bool forward, hipStream_t st) {
+  int grid = 0, sgrid = 0;
+  hipError_t e = batch_grids(&grid, &sgrid);
+  if (e != hipSuccess) return e;
+  if (dev_items) {
+    hipLaunchKernelGGL(ols_batch_setup_kernel, dim3(1), dim3(SETUP_THREADS), 0, st, dev_items, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(ols_batch_spectra_kernel, dim3(sgrid), dim3(256), 0, st, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (forward) {
+    hipLaunchKernelGGL(ols_batched_kernel, dim3(grid), dim3(256), 0, st, L);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
@@ -809,12 +1181,7 @@ ols_status_t ols_plan_ex(ols_plan_t* plan, const void* h, int32_t K, int32_t M, 
     // the derivative is a convolution with [1, -1]: one more tap of aliasing
     const int Meff = (flags & OLS_POST_DERIVATIVE) ? M + 1 : M;
     if (N == 0) {
-      double best = 1e301;
-      for (int n = OLS_MIN_FFT_LENGTH; n <= OLS_MAX_FFT_LENGTH; n *= 2) {
-        if (n < Meff) continue;
-        const double c = cost_per_output(n, Meff, K);
-        if (c < best) { best = c; N = n; }
-      }
+      N = cost_model_fft_length(K, Meff, OLS_MAX_FFT_LENGTH);
       if (N == 0) return fail(OLS_ERROR_INVALID_VALUE, "filter longer than the largest FFT length");
     }
     if (!is_pow2(N) || N < OLS_MIN_FFT_LENGTH || N > OLS_MAX_FFT_LENGTH)
@@ -1066,154 +1433,53 @@ ols_status_t ols_plan_destroy(ols_plan_t p) {
   return OLS_SUCCESS;
 }
 
-// Validates batch item i and resolves its FFT length (the caller's, or the
-// cost model's when it is 0).
-static ols_status_t batch_item_fft_length(const ols_batch_item_t& it, int i, int* N_out) {
+// Host-side check of batch item i (the same checks the device-side setup
+// repeats), with a message naming the item.
+static ols_status_t batch_item_host_check(const ols_batch_item_t& it, int i, int* N_out) {
+  const int st = batch_item_check(it.s, it.N_s, it.h, it.K, it.M, it.N, it.y, N_out);
+  if (st == 0) return OLS_SUCCESS;
   const std::string where = "item " + std::to_string(i) + ": ";
-  if (it.K < 1 || it.M < 1 || it.N_s < 0) return fail(OLS_ERROR_INVALID_VALUE, where + "K, M >= 1 and N_s >= 0 required");
-  if (!it.h || (it.N_s > 0 && (!it.s || !it.y))) return fail(OLS_ERROR_INVALID_VALUE, where + "NULL pointer");
-  if (((uintptr_t)it.s | (uintptr_t)it.y | (uintptr_t)it.h) % 8) return fail(OLS_ERROR_INVALID_VALUE, where + "pointers must be 8-byte aligned");
-  if (it.N_s > ((int64_t)1 << 56) / 8 / it.K) return fail(OLS_ERROR_INVALID_VALUE, where + "K*N_s*8 overflows");
-  if (it.N_s > 0 && ranges_overlap(it.s, (size_t)it.N_s * 8, it.y, (size_t)it.N_s * 8 * it.K))
-    return fail(OLS_ERROR_INVALID_VALUE, where + "y overlaps s");
-  int N = it.N;
-  if (N == 0) {
-    double best = 1e301;
-    for (int c = OLS_MIN_FFT_LENGTH; c <= OLS_MAX_BATCH_FFT_LENGTH; c *= 2) {
-      if (c < it.M) continue;
-      const double cost = cost_per_output(c, it.M, it.K);
-      if (cost < best) { best = cost; N = c; }
-    }
-    if (N == 0) return fail(OLS_ERROR_UNSUPPORTED, where + "filter longer than the largest batched FFT length");
-  }
-  if (!is_pow2(N) || N < OLS_MIN_FFT_LENGTH || N > OLS_MAX_BATCH_FFT_LENGTH)
-    return fail(OLS_ERROR_UNSUPPORTED, where + "batched N must be a power of two in [256, 4096]");
-  if (it.M > N) return fail(OLS_ERROR_INVALID_VALUE, where + "M must be <= N");
-  *N_out = N;
-  return OLS_SUCCESS;
+  if (st == OLS_ERROR_UNSUPPORTED)
+    return fail(OLS_ERROR_UNSUPPORTED, where + "batched N must be a power of two in [256, 4096] (or 0 with M <= 4096)");
+  return fail(OLS_ERROR_INVALID_VALUE, where + "K, M >= 1, N_s >= 0, non-NULL 8-byte aligned pointers, M <= N, "
+                                               "K*N_s*8 in range and y not overlapping s are required");
 }
 
-static size_t batch_twiddle_elems() {
-  return RunTwiddles<256>::run().size() + RunTwiddles<512>::run().size() + RunTwiddles<1024>::run().size() +
-         RunTwiddles<2048>::run().size() + RunTwiddles<4096>::run().size();
+// Workspace bytes of a batched call over these items; host checks only.
+static ols_status_t batch_bytes(const ols_batch_item_t* items, int32_t n, size_t* bytes) {
+  if (!items || n < 1) return fail(OLS_ERROR_INVALID_VALUE, "items is NULL or n < 1");
+  size_t spec = 0;
+  for (int i = 0; i < n; ++i) {
+    int N = 0;
+    const ols_status_t r = batch_item_host_check(items[i], i, &N);
+    if (r != OLS_SUCCESS) return r;
+    spec += (size_t)items[i].K * N;
+  }
+  *bytes = batch_offsets(n).spec + spec * sizeof(float2);
+  return OLS_SUCCESS;
 }
 
 ols_status_t ols_batched_workspace_size(const ols_batch_item_t* items, int32_t n, size_t* bytes) {
   try {
     if (!bytes) return fail(OLS_ERROR_INVALID_VALUE, "bytes is NULL");
     *bytes = 0;
-    if (!items || n < 1) return fail(OLS_ERROR_INVALID_VALUE, "items is NULL or n < 1");
-    size_t spec = 0;
-    for (int i = 0; i < n; ++i) {
-      int N = 0;
-      const ols_status_t r = batch_item_fft_length(items[i], i, &N);
-      if (r != OLS_SUCCESS) return r;
-      spec += (size_t)items[i].K * N;
-    }
-    *bytes = (spec + batch_twiddle_elems()) * sizeof(float2) + (size_t)n * sizeof(BatchItem);
-    return OLS_SUCCESS;
+    return batch_bytes(items, n, bytes);
   } catch (...) {
     return fail(OLS_ERROR_INTERNAL, "exception in ols_batched_workspace_size");
   }
 }
 
-ols_status_t ols_batch_plan(ols_batch_t* out, const ols_batch_item_t* items, int32_t n, ols_stream_t stream) {
+ols_status_t ols_batched(const ols_batch_item_t* dev_items, int32_t n, void* workspace, size_t ws_bytes,
+                         ols_stream_t stream) {
   try {
-    if (!out) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL");
-    *out = nullptr;
-    if (!items || n < 1) return fail(OLS_ERROR_INVALID_VALUE, "items is NULL or n < 1");
-    ols_batch_s* b = new (std::nothrow) ols_batch_s();
-    if (!b) return fail(OLS_ERROR_OUT_OF_MEMORY, "host allocation failed");
-    b->n = n;
-    b->items_host.resize(n);
-    size_t spec_elems = 0;
-    int64_t units = 0;
-    for (int i = 0; i < n; ++i) {
-      const ols_batch_item_t& it = items[i];
-      int N = 0;
-      const ols_status_t r = batch_item_fft_length(it, i, &N);
-      if (r != OLS_SUCCESS) { destroy_batch(b); return r; }
-      BatchItem& d = b->items_host[i];
-      d.s = (const float2*)it.s;
-      d.y = (float2*)it.y;
-      d.Ns = it.N_s;
-      d.K = it.K;
-      d.M = it.M;
-      d.N = N;
-      d.D = default_delay(N, it.M);
-      d.H = N - d.D;
-      d.nf = choose_nf_batched(N, it.K);
-      const int segs = 4096 / N;  // transforms per 256-thread workgroup
-      const int64_t nseg = (it.N_s + d.H - 1) / d.H;
-      d.ntiles = (nseg + segs - 1) / segs;
-      d.units = d.ntiles * ((it.K + d.nf - 1) / d.nf);
-      spec_elems += (size_t)it.K * N;
-    }
-    // The kernel's tile list takes the items by class (N, filters per unit),
-    // in the caller's order within a class, so that each workgroup meets
-    // each class in one run of tiles.
-    b->order.resize(n);
-    for (int i = 0; i < n; ++i) b->order[i] = i;
-    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
-      const BatchItem &u = b->items_host[x], &v = b->items_host[y];
-      return u.N != v.N ? u.N < v.N : u.nf < v.nf;
-    });
-    for (int k = 0; k < n; ++k) {
-      BatchItem& d = b->items_host[b->order[k]];
-      d.unit_begin = units;
-      units += d.units;
-      d.tile_begin = b->total_tiles;
-      b->total_tiles += d.ntiles;
-    }
-    b->total_units = units;
-    hipError_t e;
-    int dev = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "hipGetDevice"); }
-    if ((e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "hipDeviceGetAttribute"); }
-    int per_cu = 0;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ols_batched_kernel, 256, 0)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "occupancy query"); }
-    b->grid = (per_cu < 1 ? 1 : per_cu) * b->cus;
-    hipStream_t st = (hipStream_t)stream;
-    // twiddle tables for every batched N
-    std::vector<float2> tws[5] = {RunTwiddles<256>::run(), RunTwiddles<512>::run(), RunTwiddles<1024>::run(),
-                                  RunTwiddles<2048>::run(), RunTwiddles<4096>::run()};
-    for (int k = 0; k < 5; ++k) {
-      if (hipMalloc(&b->tw[k], tws[k].size() * sizeof(float2)) != hipSuccess) { destroy_batch(b); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "twiddle allocation"); }
-      if ((e = hipMemcpyAsync(b->tw[k], tws[k].data(), tws[k].size() * sizeof(float2), hipMemcpyHostToDevice, st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "twiddle upload"); }
-    }
-    if (hipMalloc(&b->spectra, spec_elems * sizeof(float2)) != hipSuccess) { destroy_batch(b); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "spectra allocation"); }
-    size_t off = 0;
-    for (int i = 0; i < n; ++i) {
-      BatchItem& d = b->items_host[i];
-      float2* F = b->spectra + off;
-      d.spectra = F;
-      off += (size_t)d.K * d.N;
-      const int k = ilog2(d.N) - 8;
-      e = dispatch<RunSpectra>(d.N, items[i].h, d.K, d.M, F, (const float2*)b->tw[k], st, 0, 0);
-      if (e != hipSuccess) { destroy_batch(b); return hip_fail(e, "filter spectra launch"); }
-    }
-    b->items_sorted.resize(n);
-    for (int k = 0; k < n; ++k) b->items_sorted[k] = b->items_host[b->order[k]];
-    if (hipMalloc(&b->items_dev, (size_t)n * sizeof(BatchItem)) != hipSuccess) { destroy_batch(b); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "item table allocation"); }
-    if ((e = hipMemcpyAsync(b->items_dev, b->items_sorted.data(), (size_t)n * sizeof(BatchItem), hipMemcpyHostToDevice, st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "item table upload"); }
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "batch plan synchronisation"); }
-    *out = b;
-    return OLS_SUCCESS;
-  } catch (...) {
-    return fail(OLS_ERROR_INTERNAL, "exception in ols_batch_plan");
-  }
-}
-
-ols_status_t ols_batched(ols_batch_t b, ols_stream_t stream) {
-  try {
-    if (!b) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL");
-    if (b->total_units == 0) return OLS_SUCCESS;
-    const int64_t grid = b->total_tiles < b->grid ? b->total_tiles : b->grid;
-    hipLaunchKernelGGL(ols_batched_kernel, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream,
-                       (const BatchItem*)b->items_dev, b->n, b->total_tiles, (const float2*)b->tw[0],
-                       (const float2*)b->tw[1], (const float2*)b->tw[2], (const float2*)b->tw[3],
-                       (const float2*)b->tw[4]);
-    hipError_t e = hipGetLastError();
+    if (!dev_items || n < 1) return fail(OLS_ERROR_INVALID_VALUE, "dev_items is NULL or n < 1");
+    if ((uintptr_t)dev_items % 8) return fail(OLS_ERROR_INVALID_VALUE, "dev_items must be 8-byte aligned");
+    if (!workspace || (uintptr_t)workspace % 256) return fail(OLS_ERROR_INVALID_VALUE, "workspace is NULL or not 256-byte aligned");
+    // every item needs at least K * N >= 256 spectrum elements
+    if (ws_bytes < batch_offsets(n).spec + (size_t)n * OLS_MIN_FFT_LENGTH * sizeof(float2))
+      return fail(OLS_ERROR_INVALID_VALUE, "workspace too small for n items");
+    const BatchLayout L = batch_layout(workspace, ws_bytes, n);
+    const hipError_t e = launch_batch(dev_items, L, true, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
     return OLS_SUCCESS;
   } catch (...) {
@@ -1221,19 +1487,96 @@ ols_status_t ols_batched(ols_batch_t b, ols_stream_t stream) {
   }
 }
 
+ols_status_t ols_batched_status(const void* workspace, ols_stream_t stream, int32_t* status, int32_t* bad_item) {
+  try {
+    if (!workspace || (uintptr_t)workspace % 256) return fail(OLS_ERROR_INVALID_VALUE, "workspace is NULL or not 256-byte aligned");
+    BatchHeader hd{};
+    hipError_t e = hipMemcpyAsync(&hd, workspace, sizeof(hd), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "status read-back");
+    if (status) *status = hd.status;
+    if (bad_item) *bad_item = hd.bad_item;
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_batched_status");
+  }
+}
+
+ols_status_t ols_batch_plan(ols_batch_t* out, const ols_batch_item_t* items, int32_t n, ols_stream_t stream) {
+  try {
+    if (!out) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL");
+    *out = nullptr;
+    size_t bytes = 0;
+    const ols_status_t r = batch_bytes(items, n, &bytes);
+    if (r != OLS_SUCCESS) return r;
+    ols_batch_s* b = new (std::nothrow) ols_batch_s();
+    if (!b) return fail(OLS_ERROR_OUT_OF_MEMORY, "host allocation failed");
+    b->n = n;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    int sgrid = 0;
+    if ((e = batch_grids(&b->grid, &sgrid)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "occupancy query"); }
+    if (hipMalloc(&b->ws, bytes) != hipSuccess || hipMalloc(&b->dev_items, (size_t)n * sizeof(ols_batch_item_t)) != hipSuccess) {
+      destroy_batch(b);
+      (void)hipGetLastError();
+      return fail(OLS_ERROR_OUT_OF_MEMORY, "batch allocation");
+    }
+    b->L = batch_layout(b->ws, bytes, n);
+    if ((e = hipMemcpyAsync(b->dev_items, items, (size_t)n * sizeof(ols_batch_item_t), hipMemcpyHostToDevice, st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "item upload"); }
+    // the same setup and spectra kernels as ols_batched, once
+    if ((e = launch_batch(b->dev_items, b->L, false, st)) != hipSuccess) { destroy_batch(b); return hip_fail(e, "batch setup launch"); }
+    BatchHeader hd{};
+    b->items_sorted.resize(n);
+    b->order.resize(n);
+    if ((e = hipMemcpyAsync(&hd, b->L.hdr, sizeof(hd), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(b->items_sorted.data(), b->L.items, (size_t)n * sizeof(BatchItem), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(b->order.data(), b->L.order, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+      destroy_batch(b);
+      return hip_fail(e, "batch setup read-back");
+    }
+    if (hd.status != OLS_SUCCESS) {
+      destroy_batch(b);
+      return fail(OLS_ERROR_INTERNAL, "device-side batch setup disagreed with the host checks");
+    }
+    b->total_tiles = hd.total_tiles;
+    b->pos_of.assign(n, -1);
+    for (int k = 0; k < n; ++k) {
+      b->pos_of[b->order[k]] = k;
+      b->total_units += b->items_sorted[k].units;
+    }
+    *out = b;
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_batch_plan");
+  }
+}
+
+ols_status_t ols_batch_run(ols_batch_t b, ols_stream_t stream) {
+  try {
+    if (!b) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL");
+    const hipError_t e = launch_batch(nullptr, b->L, true, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_batch_run");
+  }
+}
+
 ols_status_t ols_batch_get_info(ols_batch_t b, int64_t* total_units, int32_t* grid, int32_t* n) {
   if (!b) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL");
   if (total_units) *total_units = b->total_units;
-  if (grid) *grid = (int32_t)(b->total_tiles < b->grid ? b->total_tiles : b->grid);
+  if (grid) *grid = b->grid;
   if (n) *n = b->n;
   return OLS_SUCCESS;
 }
 
 ols_status_t ols_batch_get_item(ols_batch_t b, int32_t i, int32_t* N, int32_t* H, int32_t* D) {
   if (!b || i < 0 || i >= b->n) return fail(OLS_ERROR_INVALID_VALUE, "batch is NULL or item out of range");
-  if (N) *N = b->items_host[i].N;
-  if (H) *H = b->items_host[i].H;
-  if (D) *D = b->items_host[i].D;
+  const BatchItem& it = b->items_sorted[b->pos_of[i]];
+  if (N) *N = it.N;
+  if (H) *H = it.H;
+  if (D) *D = it.D;
   return OLS_SUCCESS;
 }
 

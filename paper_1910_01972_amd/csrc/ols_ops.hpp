@@ -364,6 +364,72 @@ OLS_HD int choose_nf_batched(int N, int K) { return (N <= BATCH_NF2_MAX_N && (K 
 // per unit only up to N = 2048 as well.
 OLS_HD int choose_nf_real(int N, int K) { return N <= BATCH_NF2_MAX_N ? choose_nf(N, K) : 1; }
 
+// ---------------------------------------------------------------------------
+// Segment geometry and FFT-length choice, shared by the host plan code and the
+// device-side batch setup so that both always reach the same answer.
+// ---------------------------------------------------------------------------
+// First kept circular position: M - 1 rounded up to a multiple of 16 samples
+// (128-byte aligned output windows) when that still leaves room, else M - 1.
+OLS_HD int default_delay(int N, int M) {
+  const int d = ((M - 1) + 15) / 16 * 16;
+  return d <= N - 1 ? d : M - 1;
+}
+
+// Cost model for N = 0: transform work per kept output sample, about
+// (K + 1) * 3.2 N log2 N + K * 4 N flops per segment over K * H kept samples.
+// Compared as exact integers (5x the work, cross-multiplied by the hops) so
+// that the host and the device pick the same N.  Returns 0 if no length in
+// [256, max_n] holds M taps.
+OLS_HD int cost_model_fft_length(int K, int M, int max_n) {
+  int best = 0;
+  unsigned __int128 best_w = 0, best_h = 1;
+  for (int n = 256; n <= max_n; n *= 2) {
+    if (n < M) continue;
+    const int h = n - default_delay(n, M);
+    if (h < 1) continue;
+    const unsigned __int128 w = (unsigned __int128)(K + 1) * 16u * (unsigned)n * (unsigned)ilog2(n) +
+                                (unsigned __int128)K * 20u * (unsigned)n;
+    if (best == 0 || w * best_h < best_w * (unsigned)h) {
+      best = n;
+      best_w = w;
+      best_h = (unsigned)h;
+    }
+  }
+  return best;
+}
+
+// Batched items: validation of one item (the checks ols_batch_plan and the
+// workspace sizing do on the host, repeated by the device-side setup of
+// ols_batched) and its FFT length.  Returns an ols_status_t value (0 = valid).
+constexpr int BATCH_MIN_N = 256, BATCH_MAX_N = 4096;
+OLS_HD int batch_item_check(const void* s, int64_t Ns, const void* h, int K, int M, int N, const void* y,
+                            int* N_out) {
+  if (K < 1 || M < 1 || Ns < 0) return 1;
+  if (!h || (Ns > 0 && (!s || !y))) return 1;
+  if (((uintptr_t)s | (uintptr_t)y | (uintptr_t)h) % 8) return 1;
+  if (Ns > ((int64_t)1 << 56) / 8 / K) return 1;
+  if (Ns > 0) {
+    const uintptr_t s0 = (uintptr_t)s, s1 = s0 + (uintptr_t)Ns * 8;
+    const uintptr_t y0 = (uintptr_t)y, y1 = y0 + (uintptr_t)Ns * 8 * (uintptr_t)K;
+    if (s0 < y1 && y0 < s1) return 1;  // y overlaps s
+  }
+  int n = N;
+  if (n == 0) {
+    n = cost_model_fft_length(K, M, BATCH_MAX_N);
+    if (n == 0) return 2;  // filter longer than the largest batched length
+  }
+  if (n < BATCH_MIN_N || n > BATCH_MAX_N || (n & (n - 1))) return 2;
+  if (M > n) return 1;
+  *N_out = n;
+  return 0;
+}
+
+// Classes of batched items, (N, filters per unit): the kernel takes the items
+// class by class (stable within a class), so that each workgroup meets each
+// class in one run of tiles.
+constexpr int BATCH_CLASSES = 10;
+OLS_HD int batch_class(int N, int nf) { return 2 * (ilog2(N) - 8) + (nf - 1); }
+
 // dh reduction order: the per-slot partial lags are summed in chunks of
 // DH_CHUNK consecutive slots (each chunk in slot order, one thread per lag
 // and chunk), then the chunk sums in chunk order.  Fixed order, no atomics.

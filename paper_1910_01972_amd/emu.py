@@ -31,6 +31,8 @@ def emu() -> ctypes.CDLL:
         L.ols_emu_wave_local.restype = I32
         L.ols_emu_backward.argtypes = [I32, P, I64, P, P, I32, I32, I32, I32, I32, P, P]
         L.ols_emu_backward.restype = I32
+        L.ols_emu_cost_model.argtypes = [I32, I32, I32]
+        L.ols_emu_cost_model.restype = I32
         for f in (L.ols_emu_forward, L.ols_emu_spectra, L.ols_emu_lds_report, L.ols_emu_geometry):
             f.restype = I32
         _emu = L
@@ -170,3 +172,8 @@ def batched(items, grid: int):
     if rc != 0:
         raise RuntimeError(f"emulator returned {rc}")
     return outs
+
+
+def cost_model(K: int, M: int, max_n: int = 8192) -> int:
+    """The library's FFT-length choice for N = 0 (host code of the C library)."""
+    return int(emu().ols_emu_cost_model(int(K), int(M), int(max_n)))

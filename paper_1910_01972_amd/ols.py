@@ -56,6 +56,25 @@ class OLSPlan:
         with torch.cuda.device(h.device):
             check(lib().ols_plan_ex(ctypes.byref(self._handle), ctypes.c_void_p(h.data_ptr()), self.K, self.M, int(N),
                                     self.flags, _stream_handle(stream)), "ols_plan_ex")
+        self._remember_filters(h)
+
+    def _remember_filters(self, h: torch.Tensor) -> None:
+        # a reference keeps the memory from being reused by another tensor, so
+        # (address, version counter) identifies the contents the spectra hold
+        self._src = h.detach()
+        self._src_version = h._version
+
+    def filters_current(self, h: torch.Tensor) -> bool:
+        """True if the plan's spectra were computed from h's present contents
+        (same memory, no in-place change since)."""
+        src = getattr(self, "_src", None)
+        return (src is not None and h.data_ptr() == src.data_ptr() and tuple(h.shape) == tuple(src.shape)
+                and h._version == self._src_version)
+
+    def ensure_filters(self, h: torch.Tensor, stream=None) -> None:
+        """Recompute the spectra from h unless they already hold its contents."""
+        if not self.filters_current(h):
+            self.update_filters(h, stream=stream)
 
     def __del__(self):
         self.close()
@@ -108,6 +127,7 @@ class OLSPlan:
             raise ValueError("filter bank shape must stay (K, M)")
         check(lib().ols_plan_update_filters(self.handle, ctypes.c_void_p(h.data_ptr()), _stream_handle(stream)),
               "ols_plan_update_filters")
+        self._remember_filters(h)
 
     def spectra(self, stream=None) -> torch.Tensor:
         """Filter spectra in natural frequency order, FFT(pad h)/N, shape (K, N)."""
@@ -174,7 +194,7 @@ class OLSConvFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, s, h, plan):
-        plan.update_filters(h.detach().contiguous())
+        plan.ensure_filters(h.detach().contiguous())
         y = plan.forward(s.detach().contiguous())
         ctx.save_for_backward(s, h)
         ctx.plan = plan
@@ -184,8 +204,8 @@ class OLSConvFunction(torch.autograd.Function):
     def backward(ctx, gy):
         s, h = ctx.saved_tensors
         plan = ctx.plan
-        # the plan may have seen other filters since this forward
-        plan.update_filters(h.detach().contiguous())
+        # recomputed only if the plan has seen other filters since this forward
+        plan.ensure_filters(h.detach().contiguous())
         ds, dh = plan.backward(s.detach().contiguous(), gy.contiguous(), need_ds=ctx.needs_input_grad[0],
                                need_dh=ctx.needs_input_grad[1])
         return ds, dh, None
@@ -219,6 +239,8 @@ class OLSBatch:
         n = len(items)
         if n < 1:
             raise ValueError("empty batch")
+        if outputs is not None and len(outputs) != n:
+            raise ValueError(f"{len(outputs)} outputs for {n} items")
         arr = (BatchItem * n)()
         self.inputs, self.outputs = [], []
         for i, it in enumerate(items):
@@ -232,6 +254,11 @@ class OLSBatch:
             y = outputs[i] if outputs is not None else torch.empty((K, s.shape[0]), dtype=torch.complex64,
                                                                    device=s.device)
             _check_c64(y, "y", 2)
+            if tuple(y.shape) != (K, int(s.shape[0])):
+                raise ValueError(f"output {i} must have shape (K, N_s) = ({K}, {int(s.shape[0])}), "
+                                 f"got {tuple(y.shape)}")
+            if y.device != s.device or h.device != s.device:
+                raise ValueError(f"item {i}: s, h and y must be on the same device")
             self.inputs.append((s, h))
             self.outputs.append(y)
             arr[i] = BatchItem(s.data_ptr(), int(s.shape[0]), h.data_ptr(), K, M, N, y.data_ptr())
@@ -255,7 +282,7 @@ class OLSBatch:
 
     def run(self, stream=None):
         """One persistent launch over every item; returns the outputs."""
-        check(lib().ols_batched(self._handle, _stream_handle(stream)), "ols_batched")
+        check(lib().ols_batch_run(self._handle, _stream_handle(stream)), "ols_batch_run")
         return self.outputs
 
     def close(self) -> None:
@@ -266,6 +293,76 @@ class OLSBatch:
 
     def __del__(self):
         self.close()
+
+
+class OLSBatched:
+    """The single-call batched path (ols_batched): the item table lives in
+    device memory and the caller owns the workspace, so one call -- setup,
+    filter spectra and the persistent forward -- allocates nothing and can be
+    captured in a hipGraph; every call reads the items (and the filters)
+    again.
+
+    items: sequence of (s [N_s], h [K][M][, N]) complex64 GPU tensors, as for
+    OLSBatch; outputs y_i [K_i][N_s_i] are allocated here or passed.
+    workspace: a uint8 GPU tensor of at least workspace_bytes, or None to
+    allocate one here.
+    """
+
+    def __init__(self, items, outputs=None, workspace=None):
+        from ._lib import BatchItem
+        n = len(items)
+        if n < 1:
+            raise ValueError("empty batch")
+        if outputs is not None and len(outputs) != n:
+            raise ValueError(f"{len(outputs)} outputs for {n} items")
+        arr = (BatchItem * n)()
+        self.inputs, self.outputs = [], []
+        device = None
+        for i, it in enumerate(items):
+            s, h = it[0], it[1]
+            N = int(it[2]) if len(it) > 2 else 0
+            _check_c64(s, "s", 1)
+            _check_c64(h, "h", 2)
+            K = int(h.shape[0])
+            y = outputs[i] if outputs is not None else torch.empty((K, s.shape[0]), dtype=torch.complex64,
+                                                                   device=s.device)
+            _check_c64(y, "y", 2)
+            if tuple(y.shape) != (K, int(s.shape[0])):
+                raise ValueError(f"output {i} must have shape (K, N_s) = ({K}, {int(s.shape[0])}), "
+                                 f"got {tuple(y.shape)}")
+            if y.device != s.device or h.device != s.device or (device is not None and s.device != device):
+                raise ValueError(f"item {i}: all tensors must be on one device")
+            device = s.device
+            self.inputs.append((s, h))
+            self.outputs.append(y)
+            arr[i] = BatchItem(s.data_ptr(), int(s.shape[0]), h.data_ptr(), K, int(h.shape[1]), N, y.data_ptr())
+        nbytes = ctypes.c_size_t()
+        check(lib().ols_batched_workspace_size(arr, n, ctypes.byref(nbytes)), "ols_batched_workspace_size")
+        self.workspace_bytes = int(nbytes.value)
+        raw = bytes(arr)
+        self.dev_items = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+        if workspace.dtype != torch.uint8 or workspace.device != device or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor on the items' device")
+        if workspace.numel() < self.workspace_bytes:
+            raise ValueError(f"workspace holds {workspace.numel()} bytes, {self.workspace_bytes} needed")
+        self.workspace = workspace
+        self.n = n
+
+    def run(self, stream=None):
+        """One ols_batched call (three launches, no allocation); returns the outputs."""
+        check(lib().ols_batched(ctypes.c_void_p(self.dev_items.data_ptr()), self.n,
+                                ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                _stream_handle(stream)), "ols_batched")
+        return self.outputs
+
+    def status(self, stream=None) -> tuple:
+        """(status, first bad item or -1) of the last call's device-side checks."""
+        st, bad = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().ols_batched_status(ctypes.c_void_p(self.workspace.data_ptr()), _stream_handle(stream),
+                                       ctypes.byref(st), ctypes.byref(bad)), "ols_batched_status")
+        return st.value, bad.value
 
 
 def ols_conv(s: torch.Tensor, h: torch.Tensor, N: int = 0, stream=None, derivative: bool = False,

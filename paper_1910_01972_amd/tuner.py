@@ -53,9 +53,21 @@ def _time_forward(plan, s, y, reps: int, warmup: int = 2) -> float:
 
 
 def synthetic(Ns: int, K: int, M: int, seed: int):
-    import workloads
-    s, h = workloads.make_signal_filters(Ns, K, M, seed=seed)
-    return torch.from_numpy(s).cuda(), torch.from_numpy(h).cuda()
+    """Timing data drawn on the GPU: signal re/im uniform[-1, 1], filter re/im
+    N(0, 1)/sqrt(M) (the values do not change the kernel's time)."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    s = torch.complex(torch.rand(Ns, device="cuda", generator=g) * 2 - 1,
+                      torch.rand(Ns, device="cuda", generator=g) * 2 - 1)
+    h = torch.complex(torch.randn(K, M, device="cuda", generator=g),
+                      torch.randn(K, M, device="cuda", generator=g)) / M ** 0.5
+    return s, h
+
+
+# The 12 cells of the FFT-length sweep: M in {32, 128, 512, 2048} x K in {1, 8, 64}
+# on a 2^25-sample signal (seeds 3000 + cell index).
+SWEEP_NS = 1 << 25
+SWEEP_CELLS = tuple((M, K, 3000 + 3 * i + j) for i, M in enumerate((32, 128, 512, 2048))
+                    for j, K in enumerate((1, 8, 64)))
 
 
 def tilings(plan) -> list:
@@ -158,9 +170,11 @@ def sweep(reps: int = 10, tune_ns: int = 1 << 22):
     """The 12 cells (M in {32, 128, 512, 2048} x K in {1, 8, 64}) on a 2^25
     sample signal: N tuned on a 2^22-sample proxy, then measured at full size.
     Prints one JSON line per cell."""
-    import workloads
+    from types import SimpleNamespace
+
     from .ols import OLSPlan
-    for wl in workloads.sweep_cells():
+    for M, K, seed in SWEEP_CELLS:
+        wl = SimpleNamespace(name=f"sweep_2p25_m{M}_k{K}", M=M, K=K, Ns=SWEEP_NS, seed=seed)
         proxy = synthetic(tune_ns, wl.K, wl.M, seed=wl.seed)
         t = tune(wl.M, wl.K, reps=reps, data=proxy)
         del proxy

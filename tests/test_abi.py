@@ -108,3 +108,38 @@ def test_batched_workspace_size_host_only():
     overlap = BI(base, 1000, base + (1 << 30), 3, 100, 512, base + 8)          # y overlaps s
     assert size([overlap])[0] == 1
     assert L.ols_batched_workspace_size(None, 1, None) == 1
+
+
+def test_batched_device_call_host_checks():
+    """ols_batched rejects NULL or misaligned pointers, n < 1 and a workspace
+    too small for n items on the host, before anything is enqueued (the fake
+    pointers are never dereferenced)."""
+    L = _lib.lib()
+    items = ctypes.c_void_p(1 << 40)
+    ws = ctypes.c_void_p(1 << 41)
+    big = 1 << 30
+    assert L.ols_batched(None, 1, ws, big, None) == 1
+    assert L.ols_batched(items, 0, ws, big, None) == 1
+    assert L.ols_batched(ctypes.c_void_p((1 << 40) + 4), 1, ws, big, None) == 1
+    assert L.ols_batched(items, 1, None, big, None) == 1
+    assert L.ols_batched(items, 1, ctypes.c_void_p((1 << 41) + 128), big, None) == 1
+    assert L.ols_batched(items, 1000, ws, 4096, None) == 1
+    assert b"workspace" in L.ols_last_error()
+    assert L.ols_batched_status(None, None, None, None) == 1
+
+
+def test_batched_workspace_grows_with_items():
+    """Workspace bytes: fixed parts grow with the item count, spectra with K x N."""
+    L = _lib.lib()
+    BI = _lib.BatchItem
+    base = 1 << 40
+
+    def size(n):
+        arr = (BI * n)(*[BI(base + (2 * i) * (1 << 30), 1000, base + (2 * i + 1) * (1 << 30), 1, 16, 256,
+                            base + (1 << 38) + i * (1 << 30)) for i in range(n)])
+        out = ctypes.c_size_t()
+        assert L.ols_batched_workspace_size(arr, n, ctypes.byref(out)) == 0
+        return out.value
+
+    s1, s2 = size(1), size(2)
+    assert s2 - s1 >= 256 * 8 and s1 % 256 == 0

@@ -262,3 +262,32 @@ def test_last_exchange_is_wave_local(N):
         assert all(local), local
     else:
         assert not local[0], local  # the first exchange crosses waves: it keeps its barriers
+
+
+def test_cost_model_choice():
+    """The integer cost model picks, for every (K, M), the length with the least
+    transform work per kept output, (K+1) 3.2 N log2 N + 4 K N over K H, among
+    powers of two N >= M in [256, max] (H = N - D, D = M-1 rounded up to 16
+    when that leaves room); checked here against the same formula in float64
+    wherever the best two lengths are not within 1e-12 of a tie."""
+    def delay(N, M):
+        d = ((M - 1) + 15) // 16 * 16
+        return d if d <= N - 1 else M - 1
+
+    for max_n in (4096, 8192):
+        for K in (1, 2, 3, 8, 16, 64, 1000):
+            for M in (1, 16, 17, 64, 100, 256, 511, 1000, 2048, 3000, 4096, 5000):
+                costs = {}
+                for N in (256, 512, 1024, 2048, 4096, 8192):
+                    if N > max_n or N < M or N - delay(N, M) < 1:
+                        continue
+                    H = N - delay(N, M)
+                    costs[N] = ((K + 1) * 3.2 * N * np.log2(N) + 4.0 * K * N) / (K * H)
+                got = emu.cost_model(K, M, max_n)
+                if not costs:
+                    assert got == 0
+                    continue
+                order = sorted(costs, key=costs.get)
+                if len(order) > 1 and abs(costs[order[0]] - costs[order[1]]) < 1e-12 * costs[order[0]]:
+                    continue
+                assert got == order[0], (K, M, max_n, got, costs)

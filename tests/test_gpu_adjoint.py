@@ -39,6 +39,30 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def rel_rows(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def loops():
+    from oracle import loops as L
+    if not L.available():
+        L.build()
+    return L
+
+
+def backward_guarded(plan, s, g, Ns):
+    """ds written into a NaN-filled buffer with guard bands on both sides."""
+    buf = torch.full((Ns + 2 * GUARD,), complex(float("nan"), float("nan")), dtype=torch.complex64, device="cuda")
+    ds = buf[GUARD:GUARD + Ns]
+    _, dh = plan.backward(s, g, ds=ds)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(buf[:GUARD].real).all()) and bool(torch.isnan(buf[GUARD + Ns:].real).all()), \
+        "guard band written"
+    assert not bool(torch.isnan(ds).any()), "ds not written everywhere"
+    return ds, dh
+
+
 CASES = [
     # (Ns, K, M, N, hop)
     (1, 1, 1, 256, None),
@@ -82,7 +106,7 @@ def test_backward_partial_outputs_and_empty(ols):
     ds, dh = plan.backward(dev(s), dev(g), need_dh=False)
     assert dh is None and rel(ds.cpu().numpy(), adjoint.grad_signal(g, h)) <= TOL
     ds, dh = plan.backward(dev(s), dev(g), need_ds=False)
-    assert ds is None and rel(dh.cpu().numpy(), adjoint.grad_filters(g, s, 50)) <= TOL
+    assert ds is None and np.all(rel_rows(dh.cpu().numpy(), adjoint.grad_filters(g, s, 50)) <= TOL)
     e = torch.empty(0, dtype=torch.complex64, device="cuda")
     _, dh0 = plan.backward(e, torch.empty((3, 0), dtype=torch.complex64, device="cuda"), need_ds=False)
     torch.cuda.synchronize()
@@ -139,6 +163,44 @@ def test_grad_workload_sampled_and_dot_products(ols):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
     plan.close()
     plan2.close()
+
+
+def test_grad_workload_full_elementwise(ols, loops):
+    """The full differentiable workload (2^22 samples, 16 filters of 512 taps,
+    N = 4096) on the persistent grid the library launches: every sample of ds
+    and every row of dh against the float64 adjoint of eq. (1) (plain loops),
+    relative L2 <= 1e-5 per row; ds written into a guarded NaN buffer."""
+    wl = workloads.WORKLOADS["grad_2p22_k16_m512"]
+    say(f"full adjoint {wl.name}")
+    s, h = workloads.make_signal_filters(wl.Ns, wl.K, wl.M, seed=wl.seed)
+    g = workloads.make_grad(wl.K, wl.Ns, seed=wl.seed)
+    plan = ols.OLSPlan(dev(h), N=wl.N)
+    ds, dh = backward_guarded(plan, dev(s), dev(g), wl.Ns)
+    ds_h, dh_h = ds.cpu().numpy(), dh.cpu().numpy()
+    plan.close()
+    r_ds = rel(ds_h, loops.grad_signal(g, h))
+    r_dh = rel_rows(dh_h, loops.grad_filters(g, s, wl.M))
+    say(f"  ds rel {r_ds:.3e}  dh worst row rel {r_dh.max():.3e}")
+    assert r_ds <= TOL
+    assert np.all(r_dh <= TOL), r_dh
+
+
+@pytest.mark.parametrize("Ns,K,M,N,hop", [(1_500_001, 5, 700, 4096, 3000), (2_000_003, 3, 1500, 8192, None),
+                                          (1_000_001, 7, 200, 2048, None)])
+def test_backward_fills_grid_elementwise(ols, loops, Ns, K, M, N, hop):
+    """Signals long enough that every persistent workgroup gets work and tiles
+    are split between workgroups (odd K, a hop that is not the default):
+    ds and every dh row element-wise against the float64 adjoint."""
+    say(f"grid-filling backward Ns={Ns} K={K} M={M} N={N} hop={hop}")
+    s, h = workloads.make_signal_filters(Ns, K, M, seed=Ns % 1000)
+    g = workloads.make_grad(K, Ns, seed=Ns % 1000)
+    plan = ols.OLSPlan(dev(h), N=N)
+    if hop is not None:
+        plan.set_hop(hop)
+    ds, dh = backward_guarded(plan, dev(s), dev(g), Ns)
+    plan.close()
+    assert rel(ds.cpu().numpy(), loops.grad_signal(g, h)) <= TOL
+    assert np.all(rel_rows(dh.cpu().numpy(), loops.grad_filters(g, s, M)) <= TOL)
 
 
 def test_finite_differences_on_slice(ols):

@@ -316,13 +316,19 @@ def test_signal_longer_than_2p31_sampled(ols):
         s[a:min(Ns, a + step)] = workloads.exact_signal(a, min(Ns, a + step), "cuda")
     plan = ols.OLSPlan(dev(h), N=N)
     H = plan.info()["H"]
-    y = plan.forward(s)
+    # output rows in a NaN-filled buffer with guard bands on both sides
+    G = 4096
+    buf = torch.full((K * Ns + 2 * G,), complex(float("nan"), float("nan")), dtype=torch.complex64, device="cuda")
+    y = buf[G:G + K * Ns].view(K, Ns)
+    plan.forward(s, y)
     torch.cuda.synchronize()
+    assert bool(torch.isnan(buf[:G].real).all()) and bool(torch.isnan(buf[G + K * Ns:].real).all()), "guard written"
+    assert not bool(torch.isnan(y).any()), "an output sample was not written"
     j = (1 << 31) // H
     idx = np.unique(np.concatenate([np.arange(0, 50), np.arange((1 << 31) - 40, (1 << 31) + 40),
                                     np.arange(j * H - 3, j * H + 3), np.arange(Ns - 60, Ns)]))
     got = y[:, torch.from_numpy(idx).cuda()].cpu().numpy()
-    del y, s
+    del y, s, buf
     torch.cuda.empty_cache()
     # the oracle sees the same exact values, rebuilt on the host window by window
     ref = np.zeros((K, idx.size), dtype=np.complex128)
