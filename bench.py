@@ -96,26 +96,188 @@ def settle_clocks(fn, settle_ms: float) -> dict:
     return {"ms": (time.perf_counter() - t0) * 1e3, "launches": n}
 
 
-def cpu_baseline(s, h, n_sample: int):
-    """The oracle (eq. 1 by definition, float64) on the first n_sample outputs
-    of every filter row; returns samples/s and the BLAS thread count."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(s, h, n_sample: int, N: int, reps: int = 3):
+    """The oracle timed on the host, best of `reps`, both of its routes: eq. (1)
+    by definition (oracle.conv.direct_conv, float64 BLAS) and the hand-written
+    radix-2 FFT overlap-and-save (oracle.conv.ols_conv, float64), each on the
+    first n_sample outputs of every filter row of the same workload; value is
+    the faster route's output samples/s."""
     from threadpoolctl import threadpool_info
 
     from oracle import conv
 
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    t0 = time.perf_counter()
-    conv.direct_conv(s[:n_sample], h)
-    dt = time.perf_counter() - t0
     K = h.shape[0]
+    routes = {}
+    for name, fn in (("direct_eq1", lambda: conv.direct_conv(s[:n_sample], h)),
+                     ("naive_fft_ols", lambda: conv.ols_conv(s[:n_sample], h, N))):
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            best = min(best, time.perf_counter() - t0)
+        routes[name] = {"s": best, "samples_per_s": K * n_sample / best}
+    top = max(routes, key=lambda k: routes[k]["samples_per_s"])
     return {
-        "value": K * n_sample / dt,
+        "value": routes[top]["samples_per_s"],
         "unit": "samples/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"eq. (1) float64 direct convolution (oracle.conv.direct_conv), first {n_sample} outputs "
-                  f"of all {K} filter rows of the same workload; {dt:.1f} s wall",
+        "sample": f"float64 oracle on the first {n_sample} outputs of all {K} filter rows of the same workload, "
+                  f"best of {reps}; value = the faster route ({top})",
+        "routes": routes,
+        "cpu_model": _cpu_model(),
+        "logical_cpus": os.cpu_count(),
     }
+
+
+def single_filter_measurement(graph_launches: int = 128, replays: int = 5) -> dict:
+    """The single-filter workload (2^20 samples, one 64-tap filter, N = 1024)
+    is a few microseconds of work, so it is timed as graph_launches forward
+    launches captured in ONE hipGraph, each on its own replica of the input
+    and output (replicas rotated so that the footprint is >= 1 GB, four times
+    the 256 MB last-level cache: HBM-cold), replayed `replays` times; also the
+    same graph on one replica (cache-hot), labelled as such."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1910_01972_amd.ols import OLSPlan
+
+    wl = workloads.WORKLOADS["single_filter_2p20"]
+    s_np, h_np = workloads.make_signal_filters(wl.Ns, wl.K, wl.M, seed=wl.seed)
+    per_replica = 8 * wl.Ns * (1 + wl.K)
+    R = -(-(1 << 30) // per_replica)
+    s0 = torch.from_numpy(s_np).cuda()
+    ss = [s0.clone() for _ in range(R)]
+    ys = [torch.empty((wl.K, wl.Ns), dtype=torch.complex64, device="cuda") for _ in range(R)]
+    plan = OLSPlan(torch.from_numpy(h_np).cuda(), N=wl.N)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    out = {"workload": wl.name, "Ns": wl.Ns, "K": wl.K, "M": wl.M, "N": wl.N, "replicas": R,
+           "footprint_GB": R * per_replica / 1e9, "launches_per_graph": graph_launches}
+    for label, idx in (("hbm_cold", lambda i: i % R), ("cache_hot", lambda i: 0)):
+        with torch.cuda.stream(stream):
+            for i in range(4):
+                plan.forward(ss[idx(i)], ys[idx(i)], stream=stream)
+        stream.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            for i in range(graph_launches):
+                plan.forward(ss[idx(i)], ys[idx(i)], stream=stream)
+        graph.replay()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(replays):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            graph.replay()
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b) * 1e3 / graph_launches)
+        us = float(np.median(times))
+        out[label] = {"us_per_launch": us, "samples_per_s": wl.K * wl.Ns / (us * 1e-6),
+                      "hbm_frac": per_replica / (us * 1e-6) / (HBM_PEAK_GBS * 1e9)}
+        del graph
+    out["hbm_floor_us"] = per_replica / (HBM_PEAK_GBS * 1e9) * 1e6
+    plan.close()
+    del ss, ys
+    torch.cuda.empty_cache()
+    return out
+
+
+def sweep_measurement(launches: int = 10, rounds: int = 3) -> dict:
+    """The FFT-length sweep: 2^25-sample signal, M in {32, 128, 512, 2048} x
+    K in {1, 8, 64}.  Per cell every candidate N >= M that keeps at least a
+    quarter of each segment is timed at full size, interleaved over `rounds`
+    rounds of `launches` launches (median per N), beside the library's
+    cost-model choice; GB/s and the HBM fraction use the algorithmic bytes."""
+    import numpy as np
+    import torch
+
+    from paper_1910_01972_amd import tuner
+    from paper_1910_01972_amd.ols import OLSPlan
+
+    cells = []
+    for M, K, seed in tuner.SWEEP_CELLS:
+        Ns = tuner.SWEEP_NS
+        s, h = tuner.synthetic(Ns, K, M, seed)
+        y = torch.empty((K, Ns), dtype=torch.complex64, device="cuda")
+        plans = {N: OLSPlan(h, N=N) for N in tuner.CANDIDATES if N >= M and 4 * (N - M + 1) >= N}
+        auto = OLSPlan(h, N=0)
+        chosen = auto.info()["N"]
+        auto.close()
+        times = {N: [] for N in plans}
+        for p in plans.values():
+            for _ in range(3):
+                p.forward(s, y)
+        for _ in range(rounds):
+            for N, p in plans.items():
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(launches)]
+                for a, b in ev:
+                    a.record()
+                    p.forward(s, y)
+                    b.record()
+                torch.cuda.synchronize()
+                times[N] += [a.elapsed_time(b) for a, b in ev]
+        med = {N: float(np.median(v)) for N, v in times.items()}
+        best = min(med, key=med.get)
+        alg = 8.0 * K * Ns + 8.0 * Ns + 8.0 * K * M
+        frac = lambda ms: alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+        cells.append({"M": M, "K": K, "cost_model_N": chosen, "cost_model_ms": med[chosen],
+                      "cost_model_frac": frac(med[chosen]), "best_N": best, "best_ms": med[best],
+                      "best_frac": frac(med[best]), "samples_per_s": K * Ns / (med[chosen] * 1e-3),
+                      "ms_per_N": {str(N): round(v, 4) for N, v in med.items()}})
+        for p in plans.values():
+            p.close()
+        del s, h, y
+        torch.cuda.empty_cache()
+    return {"Ns": tuner.SWEEP_NS, "launches": launches, "rounds": rounds, "cells": cells}
+
+
+def roof_measurement(mib: int = 2048, launches: int = 20) -> dict:
+    """Practical HBM ceilings on this GPU: the library's plain copy kernel
+    (read + write) and a write-only fill of the same bytes."""
+    import numpy as np
+    import torch
+
+    from paper_1910_01972_amd.ols import calibration_copy
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    copy_ms = timed(lambda: calibration_copy(dst, src))
+    fill_ms = timed(lambda: dst.fill_(1.0))
+    nbytes = n * 8
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "copy_GBps": 2 * nbytes / (copy_ms * 1e-3) / 1e9,
+            "fill_GBps": nbytes / (fill_ms * 1e-3) / 1e9}
 
 
 def fwd_bwd_measurement(steps: int, warmup: int) -> dict:
@@ -324,7 +486,8 @@ def main():
                          "run holds only the benchmark's launches")
     ap.add_argument("--no-tuned-batch", action="store_true",
                     help="skip the uneven batch with the autotuner's N (keeps a profile to one batch plan)")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the FFT-length sweep (2^25 samples, 12 cells)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 18)
     ap.add_argument("--settle-ms", type=float, default=1000.0,
                     help="wall time of untimed back-to-back launches before the warm-up (reported as 'settle')")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -430,11 +593,15 @@ def main():
     del y
     torch.cuda.empty_cache()
     if not args.no_side:
+        rec["practical_roof"] = roof_measurement()
+        rec["single_filter"] = single_filter_measurement()
         rec["fwd_bwd"] = fwd_bwd_measurement(min(args.steps, 100), min(args.warmup, 50))
         rec["batched"] = batched_measurement(max(3, min(args.steps, 200) // 20), 3, tuned=not args.no_tuned_batch)
         rec["variants"] = variants_measurement(min(args.steps, 100), min(args.warmup, 50))
+        if not args.no_sweep:
+            rec["sweep"] = sweep_measurement()
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(s_np, h_np, args.cpu_sample)
+        rec["cpu_baseline"] = cpu_baseline(s_np, h_np, args.cpu_sample, wl.N)
     print(json.dumps(rec), flush=True)
 
 
