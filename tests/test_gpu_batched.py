@@ -285,7 +285,9 @@ def test_batched_device_rejects_bad_items_without_writing(ols):
 
 def test_batch_output_shape_checked(ols):
     items, host, outs, buf = make_batch(ols, SPECS[:2], seed0=110)
-    bad = [outs[0], outs[1][:, :-1]]
+    K0, Ns0 = outs[0].shape
+    # contiguous but one sample short per row (item 0 is the non-empty one)
+    bad = [outs[0].reshape(-1)[:K0 * (Ns0 - 1)].view(K0, Ns0 - 1), outs[1]]
     with pytest.raises(ValueError):
         ols.OLSBatch(items, outputs=bad)
     with pytest.raises(ValueError):
