@@ -195,6 +195,32 @@ ols_status_t ols_forward(ols_plan_t plan, const void* s, int64_t N_s, void* y, o
 ols_status_t ols_backward(ols_plan_t plan, const void* s, int64_t N_s, const void* gy, void* ds, void* dh,
                           ols_stream_t stream);
 
+/*
+ * ols_backward_static -- ols_backward for callers that cannot allocate device
+ * memory (code under hipGraph capture, serving loops, harnesses that forbid
+ * hipMalloc): the adjoint's scratch (partial ds windows of tiles shared by
+ * workgroups, per-workgroup dh lag partials and their chunk sums) lives in a
+ * library-owned static device array of OLS_STATIC_SCRATCH_BYTES per device,
+ * held until the process ends, instead of plan memory.  Same arguments,
+ * outputs and kernels as ols_backward; the call allocates nothing.
+ *   - The plan must belong to the current device.
+ *   - The scratch holds the full persistent grid's partials when they fit,
+ *     otherwise as many workgroups as fit; with fewer workgroups the partial
+ *     sums are grouped differently, so results agree with ols_backward's up
+ *     to float rounding (bit-identical when the full grid fits).
+ *   - Every part of the scratch is written before it is read within a call;
+ *     nothing needs clearing.  All calls on one device share its array: calls
+ *     that may overlap in time on one device (different streams, or host
+ *     threads without stream ordering) race and give wrong results.
+ * Errors: as ols_backward, plus INVALID_VALUE when a single workgroup's scratch
+ * (2*SEGS*N + SEGS*K*M complex64 plus chunk sums) exceeds
+ * OLS_STATIC_SCRATCH_BYTES (the message gives both sizes), or when the plan
+ * was made on another device.
+ */
+#define OLS_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+ols_status_t ols_backward_static(ols_plan_t plan, const void* s, int64_t N_s, const void* gy, void* ds, void* dh,
+                                 ols_stream_t stream);
+
 /* Allocate the plan's backward workspace now (grid x 2 x SEGS x N,
  * grid x SEGS x K x M and ceil(grid x SEGS / 16) x K x M complex64,
  * grid = persistent workgroups), so that

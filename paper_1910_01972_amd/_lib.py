@@ -45,6 +45,7 @@ SIGNATURES = {
     "ols_forward": (_I32, [_P, _P, _I64, _P, _P]),
     "ols_plan_destroy": (_I32, [_P]),
     "ols_backward": (_I32, [_P, _P, _I64, _P, _P, _P, _P]),
+    "ols_backward_static": (_I32, [_P, _P, _I64, _P, _P, _P, _P]),
     "ols_plan_reserve_backward": (_I32, [_P]),
     "ols_batch_plan": (_I32, [ctypes.POINTER(_P), _P, _I32, _P]),
     "ols_batch_run": (_I32, [_P, _P]),

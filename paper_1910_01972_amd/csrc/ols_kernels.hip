@@ -13,6 +13,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <algorithm>
@@ -865,6 +866,46 @@ __global__ void ols_copy_kernel(float4* __restrict__ dst, const float4* __restri
 // ===========================================================================
 using namespace ols;
 
+// Scratch of the adjoint: partial ds windows of tiles split between
+// workgroups, per-workgroup dh lag partials and their chunk sums.  Sized for a
+// grid of persistent workgroups (bwd_ws_bytes); every part is written before
+// it is read within one call, so nothing needs clearing beforehand.
+struct BwdWorkspace {
+  int grid = 0;
+  float2* ws_ds = nullptr;    // [grid][2][SEGS][N]
+  float2* part_dh = nullptr;  // [grid][SEGS][K][M]
+  float2* sum_dh = nullptr;   // [dh_chunks(grid * SEGS)][K][M]
+};
+
+// Bytes of each part of a BwdWorkspace, each rounded up to 256 bytes.
+struct BwdWorkspaceSizes {
+  size_t ds = 0, part = 0, sums = 0;
+  size_t total() const { return ds + part + sums; }
+};
+
+inline size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+inline BwdWorkspaceSizes bwd_ws_bytes(int grid, int segs, int N, int K, int M) {
+  BwdWorkspaceSizes z;
+  z.ds = round256((size_t)grid * 2 * segs * N * sizeof(float2));
+  z.part = round256((size_t)grid * segs * K * M * sizeof(float2));
+  z.sums = round256((size_t)dh_chunks((int64_t)grid * segs) * K * M * sizeof(float2));
+  return z;
+}
+
+// Carves a workspace for `grid` workgroups out of one buffer of at least
+// bwd_ws_bytes(grid, ...).total() bytes.
+inline BwdWorkspace bwd_ws_carve(void* base, int grid, int segs, int N, int K, int M) {
+  const BwdWorkspaceSizes z = bwd_ws_bytes(grid, segs, N, K, M);
+  char* b = (char*)base;
+  BwdWorkspace w;
+  w.grid = grid;
+  w.ws_ds = (float2*)b;
+  w.part_dh = (float2*)(b + z.ds);
+  w.sum_dh = (float2*)(b + z.ds + z.part);
+  return w;
+}
+
 struct ols_plan_s {
   int K = 0, M = 0, N = 0, D = 0, H = 0;
   int device = 0;
@@ -874,10 +915,8 @@ struct ols_plan_s {
   int segs = 0;   // segments per tile
   int nf = 1;     // filters per work unit of the forward kernel
   int flags = 0;  // OLS_POST_* and OLS_REAL
-  int bwd_grid = 0;           // persistent workgroups of the adjoint kernel
-  float2* ws_ds = nullptr;    // [bwd_grid][2][SEGS][N] partial ds windows
-  float2* part_dh = nullptr;  // [bwd_grid][SEGS][K][M] dh lag partials
-  float2* sum_dh = nullptr;   // [dh_chunks(bwd_grid * SEGS)][K][M] chunk sums of part_dh
+  void* bwd_mem = nullptr;  // the adjoint's scratch, allocated by ols_plan_reserve_backward
+  BwdWorkspace bwd{};       // carved from bwd_mem for the adjoint's full grid
   float2* spectra = nullptr;
   float2* twiddles = nullptr;
 };
@@ -963,19 +1002,19 @@ struct Kern {
   static hipError_t bwd_occupancy(int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_backward_kernel<N>, GE::WG, 0);
   }
-  static hipError_t backward(const ols_plan_s* p, const float2* s, const float2* gy, int64_t Ns, float2* ds,
-                             float2* dh, hipStream_t st) {
+  static hipError_t backward(const ols_plan_s* p, const BwdWorkspace& w, const float2* s, const float2* gy,
+                             int64_t Ns, float2* ds, float2* dh, hipStream_t st) {
     const int64_t nseg = (Ns + p->H - 1) / p->H;
     const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
     const int64_t units = ntiles * p->K;
-    const int64_t grid = units < p->bwd_grid ? units : p->bwd_grid;
+    const int64_t grid = units < w.grid ? units : w.grid;
     hipLaunchKernelGGL(ols_backward_kernel<N>, dim3((unsigned)grid), dim3(GE::WG), 0, st, s, gy, Ns, p->spectra, p->K,
-                       p->M, p->H, ntiles, p->twiddles, ds, p->ws_ds, p->part_dh, ds ? 1 : 0, dh ? 1 : 0);
+                       p->M, p->H, ntiles, p->twiddles, ds, w.ws_ds, w.part_dh, ds ? 1 : 0, dh ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ds && grid > 1) {
       // one workgroup per (tile boundary, eighth of the window): H <= 8192 outputs, at most 4 per lane
-      hipLaunchKernelGGL(ols_ds_fixup_kernel<N>, dim3((unsigned)(grid - 1), 8), dim3(256), 0, st, p->ws_ds, ds, Ns,
+      hipLaunchKernelGGL(ols_ds_fixup_kernel<N>, dim3((unsigned)(grid - 1), 8), dim3(256), 0, st, w.ws_ds, ds, Ns,
                          p->K, p->H, ntiles, grid);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -984,11 +1023,11 @@ struct Kern {
       const int64_t KM = (int64_t)p->K * p->M;
       const int64_t nslots = grid * GE::SEGS, nch = dh_chunks(nslots);
       const unsigned bx = (unsigned)((KM + 255) / 256);
-      hipLaunchKernelGGL(ols_dh_chunk_kernel, dim3(bx, (unsigned)nch), dim3(256), 0, st, p->part_dh, nslots, KM,
-                         p->sum_dh);
+      hipLaunchKernelGGL(ols_dh_chunk_kernel, dim3(bx, (unsigned)nch), dim3(256), 0, st, w.part_dh, nslots, KM,
+                         w.sum_dh);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(ols_dh_reduce_kernel, dim3(bx), dim3(256), 0, st, p->sum_dh, nch, KM, dh);
+      hipLaunchKernelGGL(ols_dh_reduce_kernel, dim3(bx), dim3(256), 0, st, w.sum_dh, nch, KM, dh);
       e = hipGetLastError();
     }
     return e;
@@ -1036,9 +1075,9 @@ struct RunBwdOccupancy {
 };
 template <int N>
 struct RunBackward {
-  static hipError_t run(const ols_plan_s* p, const float2* s, const float2* gy, int64_t Ns, float2* ds, float2* dh,
-                        hipStream_t st) {
-    return Kern<N>::backward(p, s, gy, Ns, ds, dh, st);
+  static hipError_t run(const ols_plan_s* p, const BwdWorkspace& w, const float2* s, const float2* gy, int64_t Ns,
+                        float2* ds, float2* dh, hipStream_t st) {
+    return Kern<N>::backward(p, w, s, gy, Ns, ds, dh, st);
   }
 };
 template <int N>
@@ -1137,12 +1176,90 @@ bool ranges_overlap(const void* a, size_t an, const void* b, size_t bn) {
 
 void destroy_plan(ols_plan_s* p) {
   if (!p) return;
-  if (p->ws_ds) (void)hipFree(p->ws_ds);
-  if (p->part_dh) (void)hipFree(p->part_dh);
-  if (p->sum_dh) (void)hipFree(p->sum_dh);
+  if (p->bwd_mem) (void)hipFree(p->bwd_mem);
   if (p->spectra) (void)hipFree(p->spectra);
   if (p->twiddles) (void)hipFree(p->twiddles);
   delete p;
+}
+
+}  // namespace
+
+namespace {
+
+// Persistent workgroups of the adjoint kernel: as many as fit on the device.
+ols_status_t bwd_full_grid(const ols_plan_s* p, int* grid) {
+  int per_cu = 0;
+  hipError_t e = dispatch<RunBwdOccupancy>(p->N, &per_cu);
+  if (e != hipSuccess) return hip_fail(e, "occupancy query");
+  if (per_cu < 1) per_cu = 1;
+  *grid = per_cu * p->cus;
+  return OLS_SUCCESS;
+}
+
+// Host-side checks shared by the adjoint entry points.  *done is set when the
+// call is complete without the adjoint kernels (nothing asked, or N_s = 0).
+ols_status_t bwd_validate(ols_plan_t p, const void* s, int64_t Ns, const void* gy, void* ds, void* dh, hipStream_t st,
+                          bool* done) {
+  *done = false;
+  if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+  if (p->flags != OLS_POST_NONE) return fail(OLS_ERROR_UNSUPPORTED, "backward of a post-processed or R2R plan");
+  if (Ns < 0) return fail(OLS_ERROR_INVALID_VALUE, "N_s must be >= 0");
+  if (!ds && !dh) {
+    *done = true;
+    return OLS_SUCCESS;
+  }
+  if (dh && !s && Ns > 0) return fail(OLS_ERROR_INVALID_VALUE, "s is needed for dh");
+  if (Ns > 0 && !gy) return fail(OLS_ERROR_INVALID_VALUE, "gradient is NULL");
+  const uintptr_t al = (uintptr_t)s | (uintptr_t)gy | (uintptr_t)ds | (uintptr_t)dh;
+  if (al % 8) return fail(OLS_ERROR_INVALID_VALUE, "pointers must be 8-byte aligned");
+  if (Ns > ((int64_t)1 << 56) / 8 / p->K) return fail(OLS_ERROR_INVALID_VALUE, "K*N_s*8 overflows");
+  const size_t sb = (size_t)Ns * 8, gb = (size_t)Ns * 8 * p->K, hb = (size_t)p->K * p->M * 8;
+  if (ds && (ranges_overlap(ds, sb, gy, gb) || (s && ranges_overlap(ds, sb, s, sb)) || (dh && ranges_overlap(ds, sb, dh, hb))))
+    return fail(OLS_ERROR_INVALID_VALUE, "ds overlaps an input or dh");
+  if (dh && (ranges_overlap(dh, hb, gy, gb) || ranges_overlap(dh, hb, s, sb)))
+    return fail(OLS_ERROR_INVALID_VALUE, "dh overlaps an input");
+  if (Ns == 0) {  // empty signal: dh is zero, ds is empty
+    if (dh) {
+      hipLaunchKernelGGL(ols_zero_kernel, dim3(64), dim3(256), 0, st, (float2*)dh, (int64_t)p->K * p->M);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "zero launch");
+    }
+    *done = true;
+  }
+  return OLS_SUCCESS;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ols_backward_static: the adjoint with its scratch in a file-scope device
+// array instead of plan memory, for callers that cannot allocate.  In host
+// code `scratch` names a host-side shadow, not device memory: kernels only
+// ever receive the device address obtained with hipGetSymbolAddress, looked
+// up once per device (each device holds its own copy of the array).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[OLS_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
+
+ols_status_t static_scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(OLS_ERROR_INVALID_VALUE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return OLS_SUCCESS;
 }
 
 }  // namespace
@@ -1360,29 +1477,22 @@ ols_status_t ols_forward(ols_plan_t p, const void* s, int64_t Ns, void* y, ols_s
   }
 }
 
+
 ols_status_t ols_plan_reserve_backward(ols_plan_t p) {
   try {
     if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
-    if (p->ws_ds && p->part_dh && p->sum_dh) return OLS_SUCCESS;
-    int per_cu = 0;
-    hipError_t e = dispatch<RunBwdOccupancy>(p->N, &per_cu);
-    if (e != hipSuccess) return hip_fail(e, "occupancy query");
-    if (per_cu < 1) per_cu = 1;
-    const int grid = per_cu * p->cus;
-    const size_t ws = (size_t)grid * 2 * p->segs * p->N * sizeof(float2);
-    const size_t part = (size_t)grid * p->segs * p->K * p->M * sizeof(float2);
-    const size_t sums = (size_t)dh_chunks((int64_t)grid * p->segs) * p->K * p->M * sizeof(float2);
-    float2 *a = nullptr, *b = nullptr, *c = nullptr;
-    if (hipMalloc(&a, ws) != hipSuccess || hipMalloc(&b, part) != hipSuccess || hipMalloc(&c, sums) != hipSuccess) {
-      if (a) (void)hipFree(a);
-      if (b) (void)hipFree(b);
+    if (p->bwd_mem) return OLS_SUCCESS;
+    int grid = 0;
+    const ols_status_t r = bwd_full_grid(p, &grid);
+    if (r != OLS_SUCCESS) return r;
+    const size_t bytes = bwd_ws_bytes(grid, p->segs, p->N, p->K, p->M).total();
+    void* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
       (void)hipGetLastError();
       return fail(OLS_ERROR_OUT_OF_MEMORY, "backward workspace");
     }
-    p->bwd_grid = grid;
-    p->ws_ds = a;
-    p->part_dh = b;
-    p->sum_dh = c;
+    p->bwd_mem = mem;
+    p->bwd = bwd_ws_carve(mem, grid, p->segs, p->N, p->K, p->M);
     return OLS_SUCCESS;
   } catch (...) {
     return fail(OLS_ERROR_INTERNAL, "exception in ols_plan_reserve_backward");
@@ -1392,39 +1502,55 @@ ols_status_t ols_plan_reserve_backward(ols_plan_t p) {
 ols_status_t ols_backward(ols_plan_t p, const void* s, int64_t Ns, const void* gy, void* ds, void* dh,
                           ols_stream_t stream) {
   try {
-    if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
-    if (p->flags != OLS_POST_NONE) return fail(OLS_ERROR_UNSUPPORTED, "backward of a post-processed or R2R plan");
-    if (Ns < 0) return fail(OLS_ERROR_INVALID_VALUE, "N_s must be >= 0");
-    if (!ds && !dh) return OLS_SUCCESS;
-    if (dh && !s && Ns > 0) return fail(OLS_ERROR_INVALID_VALUE, "s is needed for dh");
-    if (Ns > 0 && !gy) return fail(OLS_ERROR_INVALID_VALUE, "gradient is NULL");
-    const uintptr_t al = (uintptr_t)s | (uintptr_t)gy | (uintptr_t)ds | (uintptr_t)dh;
-    if (al % 8) return fail(OLS_ERROR_INVALID_VALUE, "pointers must be 8-byte aligned");
-    if (Ns > ((int64_t)1 << 56) / 8 / p->K) return fail(OLS_ERROR_INVALID_VALUE, "K*N_s*8 overflows");
-    const size_t sb = (size_t)Ns * 8, gb = (size_t)Ns * 8 * p->K, hb = (size_t)p->K * p->M * 8;
-    if (ds && (ranges_overlap(ds, sb, gy, gb) || (s && ranges_overlap(ds, sb, s, sb)) || (dh && ranges_overlap(ds, sb, dh, hb))))
-      return fail(OLS_ERROR_INVALID_VALUE, "ds overlaps an input or dh");
-    if (dh && (ranges_overlap(dh, hb, gy, gb) || ranges_overlap(dh, hb, s, sb)))
-      return fail(OLS_ERROR_INVALID_VALUE, "dh overlaps an input");
     hipStream_t st = (hipStream_t)stream;
-    if (Ns == 0) {  // empty signal: dh is zero, ds is empty
-      if (dh) {
-        hipLaunchKernelGGL(ols_zero_kernel, dim3(64), dim3(256), 0, st, (float2*)dh, (int64_t)p->K * p->M);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "zero launch");
-      }
-      return OLS_SUCCESS;
-    }
-    if (!p->ws_ds || !p->part_dh || !p->sum_dh) {
-      const ols_status_t r = ols_plan_reserve_backward(p);
+    bool done = false;
+    ols_status_t r = bwd_validate(p, s, Ns, gy, ds, dh, st, &done);
+    if (r != OLS_SUCCESS || done) return r;
+    if (!p->bwd_mem) {
+      r = ols_plan_reserve_backward(p);
       if (r != OLS_SUCCESS) return r;
     }
-    hipError_t e = dispatch<RunBackward>(p->N, (const ols_plan_s*)p, (const float2*)s, (const float2*)gy, Ns,
-                                         (float2*)ds, (float2*)dh, st);
+    hipError_t e = dispatch<RunBackward>(p->N, (const ols_plan_s*)p, (const BwdWorkspace&)p->bwd, (const float2*)s,
+                                         (const float2*)gy, Ns, (float2*)ds, (float2*)dh, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return OLS_SUCCESS;
   } catch (...) {
     return fail(OLS_ERROR_INTERNAL, "exception in ols_backward");
+  }
+}
+
+
+ols_status_t ols_backward_static(ols_plan_t p, const void* s, int64_t Ns, const void* gy, void* ds, void* dh,
+                                 ols_stream_t stream) {
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    bool done = false;
+    ols_status_t r = bwd_validate(p, s, Ns, gy, ds, dh, st, &done);
+    if (r != OLS_SUCCESS || done) return r;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != p->device) return fail(OLS_ERROR_INVALID_VALUE, "the plan belongs to another device");
+    int grid = 0;
+    r = bwd_full_grid(p, &grid);
+    if (r != OLS_SUCCESS) return r;
+    // as many workgroups as the scratch holds, at most the full grid
+    const size_t one = bwd_ws_bytes(1, p->segs, p->N, p->K, p->M).total();
+    if (one > OLS_STATIC_SCRATCH_BYTES)
+      return fail(OLS_ERROR_INVALID_VALUE,
+                  "the adjoint of this plan needs " + std::to_string(one) + " bytes of scratch per workgroup, more than "
+                  "the " + std::to_string((size_t)OLS_STATIC_SCRATCH_BYTES) + " bytes of ols_backward_static");
+    while (grid > 1 && bwd_ws_bytes(grid, p->segs, p->N, p->K, p->M).total() > OLS_STATIC_SCRATCH_BYTES) --grid;
+    void* base = nullptr;
+    r = static_scratch_address(&base);
+    if (r != OLS_SUCCESS) return r;
+    const BwdWorkspace w = bwd_ws_carve(base, grid, p->segs, p->N, p->K, p->M);
+    e = dispatch<RunBackward>(p->N, (const ols_plan_s*)p, w, (const float2*)s, (const float2*)gy, Ns, (float2*)ds,
+                              (float2*)dh, st);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_backward_static");
   }
 }
 

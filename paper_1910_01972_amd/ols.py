@@ -161,8 +161,12 @@ class OLSPlan:
         check(lib().ols_plan_reserve_backward(self.handle), "ols_plan_reserve_backward")
 
     def backward(self, s: torch.Tensor, gy: torch.Tensor, need_ds: bool = True, need_dh: bool = True,
-                 ds: torch.Tensor | None = None, dh: torch.Tensor | None = None, stream=None):
-        """Adjoint of forward: (ds [N_s], dh [K][M]) for upstream gradient gy [K][N_s]."""
+                 ds: torch.Tensor | None = None, dh: torch.Tensor | None = None, stream=None,
+                 static_scratch: bool = False):
+        """Adjoint of forward: (ds [N_s], dh [K][M]) for upstream gradient gy [K][N_s].
+
+        static_scratch=True calls ols_backward_static: the library allocates
+        nothing (pass ds/dh to avoid the allocations here too)."""
         _check_c64(s, "s", 1)
         _check_c64(gy, "gy", 2)
         Ns = int(s.shape[0])
@@ -182,8 +186,9 @@ class OLSPlan:
                 raise ValueError("dh must have shape (K, M)")
         p_ds = ctypes.c_void_p(ds.data_ptr()) if need_ds else ctypes.c_void_p()
         p_dh = ctypes.c_void_p(dh.data_ptr()) if need_dh else ctypes.c_void_p()
-        check(lib().ols_backward(self.handle, ctypes.c_void_p(s.data_ptr()), Ns, ctypes.c_void_p(gy.data_ptr()),
-                                 p_ds, p_dh, _stream_handle(stream)), "ols_backward")
+        name = "ols_backward_static" if static_scratch else "ols_backward"
+        check(getattr(lib(), name)(self.handle, ctypes.c_void_p(s.data_ptr()), Ns, ctypes.c_void_p(gy.data_ptr()),
+                                   p_ds, p_dh, _stream_handle(stream)), name)
         return (ds if need_ds else None), (dh if need_dh else None)
 
 
