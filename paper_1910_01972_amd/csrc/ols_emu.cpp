@@ -591,12 +591,13 @@ int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t
     it.tile_begin = tiles;
     tiles += it.ntiles;
   }
-  // the device schedule: tiles of all items dealt round-robin to the grid,
+  // the device schedule (first_batch_tile, next_batch_tile,
+  // batch_workgroup_order): chunks of tiles dealt round-robin to the grid,
   // each workgroup taking its tiles in runs of one class
-  const int64_t P = tiles < grid ? tiles : grid;
-  for (int64_t b = 0; b < P; ++b) {
+  const int64_t P = grid;
+  for (int64_t blk = 0; blk < P; ++blk) {
     int i = 0;
-    int64_t t = b;
+    int64_t t = ols::first_batch_tile(ols::batch_workgroup_order(blk, P));
     int runs = 0;
     while (t < tiles) {
       while (i + 1 < n && items[i + 1].tile_begin <= t) ++i;
@@ -608,7 +609,7 @@ int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t
         const int64_t per_tile = it.units / it.ntiles;
         const int64_t a = (t - it.tile_begin) * per_tile;
         if (dispatch<RangeN>(it.N, &it, a, a + per_tile) != 0) return 3;
-        t += P;
+        t = ols::next_batch_tile(t, P);
         if (t >= tiles) break;
         while (i + 1 < n && items[i + 1].tile_begin <= t) ++i;
         if (items[i].N != N || items[i].nf != nf) break;

@@ -56,6 +56,46 @@ OLS_HD T* wave_uniform_ptr(T* p) {
   return (T*)(intptr_t)wave_uniform64((int64_t)(intptr_t)p);
 }
 
+// Pointers into device global memory.  In device code gptr<T> is a pointer in
+// the global address space: loads and stores through it compile to global and
+// buffer instructions even where the compiler cannot see that a pointer
+// points to global memory (a pointer read from a table inside a function that
+// is not inlined would otherwise give flat instructions, which also hold up
+// every LDS wait).  In host code (the emulator) it is a plain pointer.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using gptr = T*;
+#endif
+template <class T>
+OLS_HD gptr<T> to_global(T* p) {
+  return (gptr<T>)p;
+}
+// reinterpret_cast that keeps the pointer's address space
+template <class T, class U>
+OLS_HD T* rebind_ptr(U* p) {
+  return reinterpret_cast<T*>(p);
+}
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T, class U>
+OLS_HD gptr<T> rebind_ptr(__attribute__((address_space(1))) U* p) {
+  return reinterpret_cast<gptr<T>>(p);
+}
+#endif
+
+// Loads of complex values through plain or global pointers: as builtin
+// vectors (a class type such as float2 cannot be copied out of another
+// address space).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <class P>
+OLS_HD float2 load_c64(P p, int64_t i) {
+  const f32x2 v = rebind_ptr<const f32x2>(p)[i];
+  return make_float2(v.x, v.y);
+}
+
 // ---------------------------------------------------------------------------
 // Compile-time geometry of one N-point transform.
 // ---------------------------------------------------------------------------
@@ -449,8 +489,8 @@ OLS_HD void run_pass(float2 (&x)[16], const float2* tw) {
 }
 
 // Loads the twiddles lane g needs in every pass (registers for the whole kernel).
-template <int N>
-OLS_HD void load_lane_twiddles(float2 (&tw)[Geo<N>::TWR], const float2* table, int g) {
+template <int N, class P>
+OLS_HD void load_lane_twiddles(float2 (&tw)[Geo<N>::TWR], P table, int g) {
   using GE = Geo<N>;
 #pragma unroll
   for (int k = 0; k < GE::P - 1; ++k) {
@@ -460,7 +500,7 @@ OLS_HD void load_lane_twiddles(float2 (&tw)[Geo<N>::TWR], const float2* table, i
       const int l = GE::tw_index(k, g, j);
 #pragma unroll
       for (int b = 1; b < RK; ++b)
-        tw[GE::lane_tw_offset(k) + j * (RK - 1) + b - 1] = table[GE::tw_offset(k) + (b - 1) * S + l];
+        tw[GE::lane_tw_offset(k) + j * (RK - 1) + b - 1] = load_c64(table, GE::tw_offset(k) + (b - 1) * S + l);
     }
   }
 }

@@ -217,6 +217,13 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
   int64_t tile = u0 / KG;
   int rg = (int)(u0 - tile * KG);
   float2 A[16], xa[NF][16], xb[NF][16];
+  // all data lives in global memory: the batched kernel reads these pointers
+  // from its item table, where the compiler cannot infer that by itself
+  const auto s_c = to_global((const float2*)sv);
+  const auto s_r = to_global((const float*)sv);
+  const auto Fg = to_global(F);
+  const auto y_c = to_global((float2*)yv);
+  const auto y_r = to_global((float*)yv);
 
   // Transform index of this lane (a segment, or a segment pair for REAL);
   // uniform over a wave when a transform spans whole waves (G >= 64).
@@ -226,8 +233,8 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
   };
   // segment (pair) sg, forward transformed, into A (x is scratch)
   auto transform_segment = [&](float2 (&x)[16], int64_t sg) {
-    if constexpr (REAL) load_segment_pair<N>(x, (const float*)sv, Ns, sg * step - D, H, g);
-    else load_segment<N>(x, (const float2*)sv, Ns, sg * step - D, g);
+    if constexpr (REAL) load_segment_pair<N>(x, s_r, Ns, sg * step - D, H, g);
+    else load_segment<N>(x, s_c, Ns, sg * step - D, g);
     fwd_from<N, 0>(x, lds, par, tw, grp, g);
 #pragma unroll
     for (int i = 0; i < 16; ++i) A[i] = x[i];
@@ -238,7 +245,7 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const int r = q * NF + f;
-      load_spectrum<N>(x[f], F, r < K ? r : K - 1, g);
+      load_spectrum<N>(x[f], Fg, r < K ? r : K - 1, g);
     }
   };
   auto store_group = [&](const float2 (&x)[NF][16], int q, int64_t sg) {
@@ -247,11 +254,11 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
       const int r = q * NF + f;
       if (NF == 1 || r < K) {
         if constexpr (REAL)
-          store_valid_pair<N, POWER, SMODE>(x[f], (float*)yv + (int64_t)r * Ns, Ns, sg * step, D, H, g);
+          store_valid_pair<N, POWER, SMODE>(x[f], y_r + (int64_t)r * Ns, Ns, sg * step, D, H, g);
         else if constexpr (POWER)
-          store_valid_power<N, SMODE>(x[f], (float*)yv + (int64_t)r * Ns, Ns, sg * step, D, H, g);
+          store_valid_power<N, SMODE>(x[f], y_r + (int64_t)r * Ns, Ns, sg * step, D, H, g);
         else
-          store_valid<N, SMODE>(x[f], (float2*)yv + (int64_t)r * Ns, Ns, sg * step, D, H, g);
+          store_valid<N, SMODE>(x[f], y_c + (int64_t)r * Ns, Ns, sg * step, D, H, g);
       }
     }
   };
@@ -623,23 +630,57 @@ __global__ __launch_bounds__(256) void ols_batch_spectra_kernel(BatchLayout L) {
 // setup orders the items by class, so a workgroup meets each class in one
 // run.  Returns the workgroup's first tile of another class (or past the
 // end); i follows the item walk.
+// The fields of one item, read through a global pointer (see gptr).
+__device__ __forceinline__ BatchItem read_item(gptr<const BatchItem> items, int i) {
+  BatchItem r;
+  r.s = items[i].s;
+  r.y = items[i].y;
+  r.spectra = items[i].spectra;
+  r.h = items[i].h;
+  r.Ns = items[i].Ns;
+  r.unit_begin = items[i].unit_begin;
+  r.units = items[i].units;
+  r.K = items[i].K;
+  r.M = items[i].M;
+  r.N = items[i].N;
+  r.D = items[i].D;
+  r.H = items[i].H;
+  r.nf = items[i].nf;
+  r.tile_begin = items[i].tile_begin;
+  r.ntiles = items[i].ntiles;
+  return r;
+}
+
+// Where a workgroup's walk over the tiles stands between class runs: its next
+// tile, the item it is in, and the parity of its next LDS exchange buffer
+// (passed by value so that no state goes through the stack).
+struct BatchWalk {
+  int64_t t;
+  int i;
+  int par;
+};
+
 template <int N, int NF>
-__device__ __attribute__((noinline)) int64_t batched_run(const BatchItem* __restrict__ items, int nitems, int& i,
-                                                         int64_t t, int64_t total_tiles,
-                                                         const float2* __restrict__ twt, float2* lds, int& par) {
+__device__ __attribute__((noinline)) BatchWalk batched_run(const BatchItem* __restrict__ items_in, int nitems,
+                                                           BatchWalk w, int64_t total_tiles,
+                                                           const float2* __restrict__ twt, float2* lds) {
+  const gptr<const BatchItem> items = to_global(items_in);
+  int64_t t = w.t;
+  int i = w.i, par = w.par;
+  const int64_t P = gridDim.x;
   float2 tw[Geo<N>::TWR];
-  load_lane_twiddles<N>(tw, twt, threadIdx.x % Geo<N>::G);
+  load_lane_twiddles<N>(tw, to_global(twt), threadIdx.x % Geo<N>::G);
   for (;;) {
-    const BatchItem& it = items[i];
+    const BatchItem it = read_item(items, i);
     const int64_t per_tile = it.units / it.ntiles;
     const int64_t a = (t - it.tile_begin) * per_tile;
-    forward_units<N, NF, false, false, STORE_NT, false>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a,
-                                                        a + per_tile, lds, par);
-    t += gridDim.x;
-    if (t >= total_tiles) return t;
+    forward_units<N, NF, false, false, STORE_NT>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a,
+                                                 a + per_tile, lds, par);
+    t = next_batch_tile(t, P);
+    if (t >= total_tiles) return BatchWalk{t, i, par};
     // t grows, so the item walk only moves forward (items without tiles are skipped)
     while (i + 1 < nitems && items[i + 1].tile_begin <= t) ++i;
-    if (items[i].N != N || items[i].nf != NF) return t;
+    if (items[i].N != N || items[i].nf != NF) return BatchWalk{t, i, par};
   }
 }
 
@@ -648,13 +689,12 @@ __device__ __attribute__((noinline)) int64_t batched_run(const BatchItem* __rest
 // function, which would drop the whole kernel to one wave per SIMD.
 
 template <int N>
-__device__ __forceinline__ int64_t batched_class(const BatchItem* __restrict__ items, int nitems, int& i, int64_t t,
-                                                 int64_t total_tiles, const float2* __restrict__ twt, float2* lds,
-                                                 int& par) {
+__device__ __forceinline__ BatchWalk batched_class(const BatchItem* __restrict__ items, int nitems, BatchWalk w,
+                                                   int64_t total_tiles, const float2* __restrict__ twt, float2* lds) {
   if constexpr (N <= BATCH_NF2_MAX_N) {
-    if (items[i].nf == 2) return batched_run<N, 2>(items, nitems, i, t, total_tiles, twt, lds, par);
+    if (to_global(items)[w.i].nf == 2) return batched_run<N, 2>(items, nitems, w, total_tiles, twt, lds);
   }
-  return batched_run<N, 1>(items, nitems, i, t, total_tiles, twt, lds, par);
+  return batched_run<N, 1>(items, nitems, w, total_tiles, twt, lds);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ols_batched_kernel(BatchLayout L) {
@@ -664,28 +704,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void o
   const int64_t total_tiles = L.hdr->total_tiles;
   const BatchItem* __restrict__ items = L.items;
   const int nitems = L.n;
-  // Tiles of all items, in the setup's item order, dealt round-robin to the
-  // workgroups: workgroup b takes tiles b, b + P, b + 2P, ... with all of
-  // each tile's filters.  At any moment the whole grid works on neighbouring
-  // tiles of one or two items, so every XCD keeps those items' filter
-  // spectra in its L2 (balanced contiguous unit ranges spread the grid over
-  // all items at once and re-read the spectra from HBM: 19 % slower on the
-  // uneven batch).  The imbalance is at most one tile per workgroup.
-  int par = 0;
-  int i = 0;
-  int64_t t = blockIdx.x;
-  while (t < total_tiles) {
-    while (i + 1 < nitems && items[i + 1].tile_begin <= t) ++i;
+  // Tiles of all items, in the setup's item order, dealt round-robin in
+  // chunks to the workgroups (first_batch_tile, next_batch_tile,
+  // batch_workgroup_order), each tile with all of its filters.  At any moment
+  // the whole grid works on neighbouring tiles of one or two items, so the L2s
+  // keep those items' filter spectra (balanced contiguous unit ranges spread
+  // the grid over all items at once and re-read the spectra from HBM: 19 %
+  // slower on the uneven batch).  The imbalance is at most one chunk per
+  // workgroup.
+  const int64_t P = gridDim.x;
+  BatchWalk w{first_batch_tile(batch_workgroup_order(blockIdx.x, P)), 0, 0};
+  const gptr<const BatchItem> gitems = to_global(items);
+  while (w.t < total_tiles) {
+    while (w.i + 1 < nitems && gitems[w.i + 1].tile_begin <= w.t) ++w.i;
     // items of another class lay out the LDS buffers differently, and
     // single-wave transforms exchange without barriers: every wave must have
     // finished with the previous run's buffers
     __syncthreads();
-    switch (items[i].N) {
-      case 256: t = batched_class<256>(items, nitems, i, t, total_tiles, L.tw[0], lds, par); break;
-      case 512: t = batched_class<512>(items, nitems, i, t, total_tiles, L.tw[1], lds, par); break;
-      case 1024: t = batched_class<1024>(items, nitems, i, t, total_tiles, L.tw[2], lds, par); break;
-      case 2048: t = batched_class<2048>(items, nitems, i, t, total_tiles, L.tw[3], lds, par); break;
-      default: t = batched_class<4096>(items, nitems, i, t, total_tiles, L.tw[4], lds, par); break;
+    switch (gitems[w.i].N) {
+      case 256: w = batched_class<256>(items, nitems, w, total_tiles, L.tw[0], lds); break;
+      case 512: w = batched_class<512>(items, nitems, w, total_tiles, L.tw[1], lds); break;
+      case 1024: w = batched_class<1024>(items, nitems, w, total_tiles, L.tw[2], lds); break;
+      case 2048: w = batched_class<2048>(items, nitems, w, total_tiles, L.tw[3], lds); break;
+      default: w = batched_class<4096>(items, nitems, w, total_tiles, L.tw[4], lds); break;
     }
   }
 }

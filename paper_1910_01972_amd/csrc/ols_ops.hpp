@@ -11,8 +11,8 @@ namespace ols {
 // start = j*H - D (D >= M-1 samples of history, sec. 3.2); samples outside
 // [0, N_s) read as zero.  Register reg of lane g receives the sample at
 // position g + time_pos_const(reg) of the segment.
-template <int N>
-OLS_HD void load_segment(float2 (&x)[16], const float2* __restrict__ s, int64_t Ns, int64_t start, int g) {
+template <int N, class P>
+OLS_HD void load_segment(float2 (&x)[16], P __restrict__ s, int64_t Ns, int64_t start, int g) {
   // valid positions p satisfy lo <= p < hi (clamped into [0, N])
   const int64_t lo64 = -start, hi64 = Ns - start;
   const int lo = lo64 <= 0 ? 0 : (lo64 >= N ? N : (int)lo64);
@@ -20,7 +20,7 @@ OLS_HD void load_segment(float2 (&x)[16], const float2* __restrict__ s, int64_t 
 #pragma unroll
   for (int reg = 0; reg < 16; ++reg) {
     const int p = g + time_pos_const<N>(reg);
-    x[reg] = (p >= lo && p < hi) ? s[start + p] : make_float2(0.f, 0.f);
+    x[reg] = (p >= lo && p < hi) ? load_c64(s, start + p) : make_float2(0.f, 0.f);
   }
 }
 
@@ -69,16 +69,16 @@ OLS_HD void load_filter_real(float2 (&x)[16], const float* __restrict__ h, int M
 // real convolutions in the real and imaginary parts, so the pair costs one
 // complex FFT of length N and needs no split of the spectra.  start is the
 // window start of segment 2q; segment 2q+1 starts H samples later.
-template <int N>
-OLS_HD void load_segment_pair(float2 (&x)[16], const float* __restrict__ s, int64_t Ns, int64_t start, int H, int g) {
+template <int N, class P>
+OLS_HD void load_segment_pair(float2 (&x)[16], P __restrict__ s, int64_t Ns, int64_t start, int H, int g) {
   const int64_t lo0 = -start, hi0 = Ns - start;
   const int lo_a = lo0 <= 0 ? 0 : (lo0 >= N ? N : (int)lo0);
   const int hi_a = hi0 <= 0 ? 0 : (hi0 >= N ? N : (int)hi0);
   const int64_t lo1 = lo0 - H, hi1 = hi0 - H;
   const int lo_b = lo1 <= 0 ? 0 : (lo1 >= N ? N : (int)lo1);
   const int hi_b = hi1 <= 0 ? 0 : (hi1 >= N ? N : (int)hi1);
-  const float* sa = s + start;
-  const float* sb = sa + H;
+  const P sa = s + start;
+  const P sb = sa + H;
 #pragma unroll
   for (int reg = 0; reg < 16; ++reg) {
     const int p = g + time_pos_const<N>(reg);
@@ -94,12 +94,12 @@ OLS_HD void load_segment_pair(float2 (&x)[16], const float* __restrict__ s, int6
 template <int N>
 OLS_HD int spectrum_offset(int reg, int g) { return (((reg >> 1) * Geo<N>::G + g) << 1) + (reg & 1); }
 
-template <int N>
-OLS_HD void load_spectrum(float2 (&f)[16], const float2* __restrict__ F, int r, int g) {
-  const float4* Fr = reinterpret_cast<const float4*>(F + (int64_t)r * N);
+template <int N, class P>
+OLS_HD void load_spectrum(float2 (&f)[16], P __restrict__ F, int r, int g) {
+  const auto Fr = rebind_ptr<const f32x4>(F + (int64_t)r * N);
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const float4 v = Fr[j * Geo<N>::G + g];
+    const f32x4 v = Fr[j * Geo<N>::G + g];
     f[2 * j] = make_float2(v.x, v.y);
     f[2 * j + 1] = make_float2(v.z, v.w);
   }
@@ -143,8 +143,9 @@ OLS_HD void spectrum_product(float2 (&x)[16], const float2 (&A)[16], const float
 // near the register limit keep the cheaper forms.
 enum StoreMode { STORE_PLAIN = 0, STORE_NT = 1, STORE_NT_WHOLE = 2 };
 
-template <int MODE, typename T>
-OLS_HD void out_store(T* p, T v) {
+// P: float* or gptr<float> (float2* or gptr<float2> for the complex form)
+template <int MODE, typename P>
+OLS_HD void out_store(P p, float v) {
 #if defined(__HIP_DEVICE_COMPILE__)
   if constexpr (MODE != STORE_PLAIN) {
     __builtin_nontemporal_store(v, p);
@@ -154,8 +155,8 @@ OLS_HD void out_store(T* p, T v) {
   *p = v;
 }
 
-template <int MODE>
-OLS_HD void out_store(float2* p, float2 v) {
+template <int MODE, typename P>
+OLS_HD void out_store(P p, float2 v) {
   out_store<MODE>(&p->x, v.x);
   out_store<MODE>(&p->y, v.y);
 }
@@ -165,8 +166,9 @@ constexpr int CPOL_NT = 2;  // cache-policy operand of the buffer builtins: nt
 
 // Raw buffer over [base, base + bytes): accesses at offsets >= bytes are
 // dropped by the range check.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(void* base, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, 0x00020000);
+template <class P>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(P base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, bytes, 0x00020000);
 }
 
 template <int CPOL>
@@ -218,6 +220,7 @@ OLS_HD int granule_phase(const T* p) {
 // H / LS.  The choice of policy never changes what is written.
 template <int N, int MODE, typename T, typename V>
 OLS_HD void store_segment(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H, int g, V val) {
+  // T is float2 or float, with the pointer's address space (gptr) if any
   constexpr int LS = 64 / (int)sizeof(T);                // outputs per 64-byte granule
   constexpr int C = Geo<N>::G < 64 ? Geo<N>::G : 64;     // positions per store instruction
   static_assert(C % LS == 0, "chunks hold whole granules");
@@ -273,15 +276,13 @@ struct Power {
   OLS_HD float operator()(float2 v) const { return fmaf(v.x, v.x, v.y * v.y); }
 };
 
-template <int N, int MODE = STORE_PLAIN>
-OLS_HD void store_valid(const float2 (&x)[16], float2* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H,
-                        int g) {
+template <int N, int MODE = STORE_PLAIN, class P>
+OLS_HD void store_valid(const float2 (&x)[16], P yrow, int64_t Ns, int64_t out0, int D, int H, int g) {
   store_kept<N, MODE>(x, yrow, Ns, out0, D, H, g, Identity());
 }
 
-template <int N, int MODE = STORE_PLAIN>
-OLS_HD void store_valid_power(const float2 (&x)[16], float* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H,
-                              int g) {
+template <int N, int MODE = STORE_PLAIN, class P>
+OLS_HD void store_valid_power(const float2 (&x)[16], P yrow, int64_t Ns, int64_t out0, int D, int H, int g) {
   store_kept<N, MODE>(x, yrow, Ns, out0, D, H, g, Power());
 }
 
@@ -341,9 +342,8 @@ OLS_HD void zero_lags(float2* __restrict__ part, int M, int g) {
 // Store of a segment pair (R2R): the real part holds segment 2q's output,
 // written from out0 = 2q*H, the imaginary part segment 2q+1's, written from
 // out0 + H; each with its own end bound.  POWER squares each sample.
-template <int N, bool POWER, int MODE = STORE_PLAIN>
-OLS_HD void store_valid_pair(const float2 (&x)[16], float* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H,
-                             int g) {
+template <int N, bool POWER, int MODE = STORE_PLAIN, class P>
+OLS_HD void store_valid_pair(const float2 (&x)[16], P yrow, int64_t Ns, int64_t out0, int D, int H, int g) {
   store_segment<N, MODE>(yrow, Ns, out0, D, H, g,
                          [&](int reg) { return POWER ? x[reg].x * x[reg].x : x[reg].x; });
   store_segment<N, MODE>(yrow, Ns, out0 + H, D, H, g,
@@ -429,6 +429,23 @@ OLS_HD int batch_item_check(const void* s, int64_t Ns, const void* h, int K, int
 // class in one run of tiles.
 constexpr int BATCH_CLASSES = 10;
 OLS_HD int batch_class(int N, int nf) { return 2 * (ilog2(N) - 8) + (nf - 1); }
+
+// Schedule of the batched kernel (the device kernel and the host emulator
+// both walk it through these functions).  Tiles of all items, numbered in the
+// kernel's item order, are dealt to the P persistent workgroups round-robin:
+// workgroup b takes tiles b, b + P, b + 2P, ..., so the grid as a whole works
+// on a window of neighbouring tiles of one or two items (whose filter spectra
+// then stay in L2).  Dealing chunks of 2-8 consecutive tiles instead measured
+// 4-18 % slower on the uneven batch.
+OLS_HD int64_t first_batch_tile(int64_t b) { return b; }
+OLS_HD int64_t next_batch_tile(int64_t t, int64_t P) { return t + P; }
+// Workgroup index b of launch index blk: the hardware deals workgroups to the
+// 8 XCDs round-robin by launch index, so consecutive b (consecutive chunks of
+// a round, which share overlap samples and spectra) are put on one XCD and
+// its L2.  A permutation of [0, P).
+OLS_HD int64_t batch_workgroup_order(int64_t blk, int64_t P) {
+  return P % 8 == 0 ? (blk % 8) * (P / 8) + blk / 8 : blk;
+}
 
 // dh reduction order: the per-slot partial lags are summed in chunks of
 // DH_CHUNK consecutive slots (each chunk in slot order, one thread per lag
