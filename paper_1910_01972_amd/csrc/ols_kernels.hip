@@ -630,24 +630,27 @@ __global__ __launch_bounds__(256) void ols_batch_spectra_kernel(BatchLayout L) {
 // setup orders the items by class, so a workgroup meets each class in one
 // run.  Returns the workgroup's first tile of another class (or past the
 // end); i follows the item walk.
-// The fields of one item, read through a global pointer (see gptr).
+// The fields of one item, read through a global pointer (see gptr).  The
+// whole workgroup works on one item at a time (i is uniform), so the fields
+// are declared wave-uniform: address arithmetic stays scalar and the store
+// descriptors need no per-lane loop.
 __device__ __forceinline__ BatchItem read_item(gptr<const BatchItem> items, int i) {
   BatchItem r;
-  r.s = items[i].s;
-  r.y = items[i].y;
-  r.spectra = items[i].spectra;
-  r.h = items[i].h;
-  r.Ns = items[i].Ns;
-  r.unit_begin = items[i].unit_begin;
-  r.units = items[i].units;
-  r.K = items[i].K;
-  r.M = items[i].M;
-  r.N = items[i].N;
-  r.D = items[i].D;
-  r.H = items[i].H;
-  r.nf = items[i].nf;
-  r.tile_begin = items[i].tile_begin;
-  r.ntiles = items[i].ntiles;
+  r.s = wave_uniform_ptr(items[i].s);
+  r.y = wave_uniform_ptr(items[i].y);
+  r.spectra = wave_uniform_ptr(items[i].spectra);
+  r.h = wave_uniform_ptr(items[i].h);
+  r.Ns = wave_uniform64(items[i].Ns);
+  r.unit_begin = wave_uniform64(items[i].unit_begin);
+  r.units = wave_uniform64(items[i].units);
+  r.K = __builtin_amdgcn_readfirstlane(items[i].K);
+  r.M = __builtin_amdgcn_readfirstlane(items[i].M);
+  r.N = __builtin_amdgcn_readfirstlane(items[i].N);
+  r.D = __builtin_amdgcn_readfirstlane(items[i].D);
+  r.H = __builtin_amdgcn_readfirstlane(items[i].H);
+  r.nf = __builtin_amdgcn_readfirstlane(items[i].nf);
+  r.tile_begin = wave_uniform64(items[i].tile_begin);
+  r.ntiles = wave_uniform64(items[i].ntiles);
   return r;
 }
 
@@ -674,8 +677,8 @@ __device__ __attribute__((noinline)) BatchWalk batched_run(const BatchItem* __re
     const BatchItem it = read_item(items, i);
     const int64_t per_tile = it.units / it.ntiles;
     const int64_t a = (t - it.tile_begin) * per_tile;
-    forward_units<N, NF, false, false, STORE_NT>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a,
-                                                 a + per_tile, lds, par);
+    forward_units<N, NF, false, false, STORE_NT_WHOLE>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a,
+                                                       a + per_tile, lds, par);
     t = next_batch_tile(t, P);
     if (t >= total_tiles) return BatchWalk{t, i, par};
     // t grows, so the item walk only moves forward (items without tiles are skipped)

@@ -134,9 +134,9 @@ OLS_HD void spectrum_product(float2 (&x)[16], const float2 (&A)[16], const float
 // segment edge) is written with the default policy instead, so that its two
 // partial writes can merge in L2 before they go to HBM: with non-temporal
 // partial writes the forward kernel ran 1.5-1.75x slower when its rows were
-// off the grid, with the split policy 1.15x.  The batched kernel keeps
-// non-temporal stores throughout: its per-lane stores measured faster that
-// way on rows of uneven length.
+// off the grid, with the split policy 1.15x.  The batched kernel uses the
+// split policy too (its rows, of arbitrary length, are mostly off the grid;
+// the uneven batch ran 13 % faster with every row on the grid).
 // How a kernel writes its outputs: plain per-lane predicated stores,
 // non-temporal predicated stores, or non-temporal stores for whole granules
 // only (buffer stores when G >= 64, predicated ones otherwise).  Kernels
@@ -230,7 +230,11 @@ OLS_HD void store_segment(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D,
   const bool whole = l >= c && l - c + LS <= C;
 #if defined(__HIP_DEVICE_COMPILE__)
   if constexpr (MODE == STORE_NT_WHOLE && Geo<N>::G >= 64) {
-    const __amdgpu_buffer_rsrc_t rs = out_rsrc(yrow + out0, cnt * (int)sizeof(T));
+    // a wave holds one segment here, so its row, first output and count are
+    // wave-uniform; saying so keeps the descriptor in scalar registers (the
+    // compiler cannot always prove it, and would loop over the lanes)
+    const __amdgpu_buffer_rsrc_t rs =
+        out_rsrc(wave_uniform_ptr(yrow + out0), __builtin_amdgcn_readfirstlane(cnt * (int)sizeof(T)));
     if (whole) {
 #pragma unroll
       for (int reg = 0; reg < 16; ++reg)
