@@ -58,9 +58,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, launch: dict):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current device code and the same launch shape; else None."""
+def profile_record(workload: str, launch: dict):
+    """The committed rocprofv3 counter summary of the forward kernel (HBM bytes
+    and VALU instructions per launch), if it was taken on the current device
+    code and the same launch shape; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_ols_forward_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -68,7 +69,23 @@ def measured_traffic(workload: str, launch: dict):
         rec = json.load(f)
     if rec.get("kernel_hash") != kernel_hash() or rec.get("launch") != launch:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+# VALU issue rate of the chip: 256 CUs x 4 SIMDs, one wave64 instruction per
+# SIMD every 4 cycles, at the 2.4 GHz peak engine clock (packed FP32 unused).
+VALU_WAVE_INSTR_PER_S = 256 * 4 / 4 * 2.4e9
+
+
+def floors(alg_bytes: float, rec) -> dict:
+    """Lower bounds on the launch time: HBM (algorithmic bytes at the 8 TB/s
+    peak) and VALU (the profiled wave64 VALU instructions at the peak issue
+    rate); 'binding' names the larger one."""
+    hbm_ms = alg_bytes / (HBM_PEAK_GBS * 1e9) * 1e3
+    valu = rec.get("valu_instr_per_launch") if rec else None
+    valu_ms = valu / VALU_WAVE_INSTR_PER_S * 1e3 if valu else None
+    binding = "hbm" if valu_ms is None or hbm_ms >= valu_ms else "valu"
+    return {"hbm_ms": hbm_ms, "valu_ms": valu_ms, "valu_instr_per_launch": valu, "binding": binding}
 
 
 def launch_spread(ms) -> dict:
@@ -555,7 +572,8 @@ def main():
     # signal read once (8 B/sample), the filter taps once
     alg_bytes = 8.0 * wl.K * wl.Ns + 8.0 * wl.Ns + 8.0 * wl.K * wl.M
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(WORKLOAD, launch_key)
+    prof = profile_record(WORKLOAD, launch_key)
+    traffic = prof.get("hbm_bytes_per_launch") if prof else None
 
     rec = {
         "metric": METRIC,
@@ -576,6 +594,7 @@ def main():
             "grid": launch["grid"], "block": launch["block"], "cus": launch["cus"], "filters_per_unit": nf,
         },
         "roofline": {
+            # the metric is the HBM roofline; "floors" says which floor binds
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -586,6 +605,7 @@ def main():
             "kernel_ms": kernel_ms,
             "launch_ms": launch_spread(launch_ms),
             "alg_bytes_per_launch": alg_bytes,
+            "floors": floors(alg_bytes, prof),
         },
         "settle": settle,
     }

@@ -831,13 +831,187 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_backward_kernel(
   finish_tile();
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint with paired segments (N <= 2048).  dh_r takes the first M lags of
+// IFFT(sum_j conj(S_j)/N * G_{r,j}) over the segments j, and the inverse
+// transform is linear, so the products of two segments may be added before a
+// single inverse.  The workgroup holds BwdGeo<N>::SEGS transforms; groups 2p
+// and 2p+1 form a pair working on two neighbouring segments of one tile.  A
+// unit is (tile, filter pair r = 2q, 2q+1): every group forward transforms
+// its segment's gradient window for both filters (both feed its ds
+// accumulator), keeps the product for the filter it collects (the parity of
+// its group index) and hands the other product to its partner through LDS;
+// then each group adds the partner's product to its own and runs one inverse
+// for its filter.  Per (segment, filter): one forward transform and half an
+// inverse, against one of each in ols_backward_kernel, and half the dh
+// read-modify-writes.  A filter index past K (odd K) is transformed like the
+// last filter and then ignored, so that every group meets the same barriers.
+// ---------------------------------------------------------------------------
+template <int N>
+struct BwdGeo {
+  using GE = Geo<N>;
+  // two transforms at least (a 512-thread workgroup at N = 4096, were it used)
+  static constexpr int WG = GE::WG / GE::G >= 2 ? GE::WG : 2 * GE::G;
+  static constexpr int SEGS = WG / GE::G;
+  static constexpr int lds_e(int e) { return GE::pad(e, SEGS * N - 1) + 1; }
+  static constexpr int lds_max(int e) { return e < 0 ? 1 : (lds_e(e) > lds_max(e - 1) ? lds_e(e) : lds_max(e - 1)); }
+  static constexpr int XLDS = lds_max(GE::P - 2);  // exchange buffer (float2)
+  static constexpr int HLDS = SEGS * N;            // hand-over buffer (float2)
+  static_assert(SEGS % 2 == 0, "groups come in pairs");
+};
+
+// One exchange through a single LDS buffer: the buffer is reused by the next
+// exchange, so transforms that span several waves also need the trailing
+// barrier (single-wave transforms exchange in program order).
+template <int N, int E, int KW, int KR>
+__device__ __forceinline__ void exchange_single(float2 (&x)[16], float2* buf, int grp, int g) {
+  lds_store<N, E, KW>(buf, x, grp, g);
+  exchange_sync<N>();
+  lds_load<N, E, KR>(buf, x, grp, g);
+  if constexpr (Geo<N>::G > 64) __syncthreads();
+}
+
+template <int N, int K>
+__device__ __forceinline__ void fwd_single(float2 (&x)[16], float2* buf, const float2* tw, int grp, int g) {
+  run_pass<N, K, false>(x, tw + Geo<N>::lane_tw_offset(K));
+  if constexpr (K + 1 < Geo<N>::P) {
+    exchange_single<N, K, K, K + 1>(x, buf, grp, g);
+    fwd_single<N, K + 1>(x, buf, tw, grp, g);
+  }
+}
+
+template <int N, int K>
+__device__ __forceinline__ void inv_single(float2 (&x)[16], float2* buf, const float2* tw, int grp, int g) {
+  inverse_pass<N, K>(x, tw + Geo<N>::lane_tw_offset(K));
+  if constexpr (K > 0) {
+    exchange_single<N, K - 1, K, K - 1>(x, buf, grp, g);
+    inv_single<N, K - 1>(x, buf, tw, grp, g);
+  }
+}
+
+// Synchronisation of the hand-over between the two groups of a pair: a fence
+// when the pair shares a wave, a barrier otherwise.
+template <int N>
+__device__ __forceinline__ void pair_sync() {
+  if constexpr (2 * Geo<N>::G <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(BwdGeo<N>::WG) __attribute__((amdgpu_waves_per_eu(2))) void ols_backward_pair_kernel(
+    const float2* __restrict__ s, const float2* __restrict__ gy, int64_t Ns, const float2* __restrict__ F, int K,
+    int M, int H, int64_t ntiles, const float2* __restrict__ twt, float2* __restrict__ ds,
+    float2* __restrict__ ws_ds, float2* __restrict__ part_dh, int want_ds, int want_dh) {
+  using GE = Geo<N>;
+  using BG = BwdGeo<N>;
+  __shared__ float2 lds[BG::XLDS + BG::HLDS];
+  float2* const xbuf = lds;
+  float2* const hbuf = lds + BG::XLDS;
+  const int tid = threadIdx.x;
+  const int grp = tid / GE::G, g = tid - grp * GE::G;
+  const int side = grp & 1;  // parity of the filters this group collects
+  const int KP = (K + 1) / 2;
+  const int64_t P = gridDim.x, b = blockIdx.x;
+  const int64_t U = ntiles * KP;
+  const int64_t u0 = first_unit(U, P, b), u1 = first_unit(U, P, b + 1);
+  if (u0 >= u1) return;  // uniform over the workgroup
+
+  float2 tw[GE::TWR];
+  load_lane_twiddles<N>(tw, twt, g);
+  float2* part = part_dh + (b * BG::SEGS + grp) * (int64_t)K * M;
+  if (want_dh)
+    for (int r = 0; r < K; ++r) zero_lags<N>(part + (int64_t)r * M, M, g);
+
+  const int64_t t_first = u0 / KP;
+  int64_t tile = t_first;
+  int q = (int)(u0 - tile * KP);
+  float2 S[16], E[16], mine[16], x[16], f[16];
+  auto segment_of = [&](int64_t t) -> int64_t {
+    const int64_t sg = t * BG::SEGS + grp;
+    return GE::G >= 64 ? wave_uniform64(sg) : sg;
+  };
+  int64_t seg = segment_of(tile);
+
+  auto start_tile = [&]() {
+    seg = segment_of(tile);
+    if (want_dh) {
+      load_window<N>(x, s, Ns, seg * H, H, g);
+      fwd_single<N, 0>(x, xbuf, tw, grp, g);
+      conj_scaled(S, x, 1.0f / (float)N);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) E[i] = make_float2(0.f, 0.f);
+  };
+  auto finish_tile = [&]() {
+    if (!want_ds) return;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = E[i];
+    inv_single<N, GE::P - 1>(x, xbuf, tw, grp, g);
+    const bool complete = tile * KP >= u0 && (tile + 1) * KP <= u1;
+    if (complete) {
+      store_valid<N>(x, ds, Ns, seg * H, 0, H, g);
+    } else {
+      const int slot = tile == t_first ? 0 : 1;
+      float2* w = ws_ds + ((b * 2 + slot) * BG::SEGS + grp) * (int64_t)N;
+      store_valid<N>(x, w, (int64_t)H, 0, 0, H, g);
+    }
+  };
+  // gradient window of filter r (r < K) of this group's segment, forward
+  // transformed into x and accumulated into E when it is a real filter
+  auto gradient_spectrum = [&](int r) {
+    const bool real_filter = r < K;
+    const int rr = real_filter ? r : K - 1;
+    load_window<N>(x, gy + (int64_t)rr * Ns, Ns, seg * H, N, g);
+    fwd_single<N, 0>(x, xbuf, tw, grp, g);
+    if (want_ds && real_filter) {
+      load_spectrum<N>(f, F, rr, g);
+      acc_conj_product(E, x, f);
+    }
+  };
+
+  start_tile();
+  for (int64_t u = u0; u < u1; ++u) {
+    if (q == KP) {
+      finish_tile();
+      q = 0;
+      ++tile;
+      start_tile();
+    }
+    const int r_other = 2 * q + (1 - side), r_own = 2 * q + side;
+    // the partner's filter first: its product goes to the hand-over buffer
+    gradient_spectrum(r_other);
+    if (want_dh) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) hbuf[(grp * 16 + i) * GE::G + g] = cmul(S[i], x[i]);
+    }
+    gradient_spectrum(r_own);
+    if (want_dh) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) mine[i] = cmul(S[i], x[i]);
+      pair_sync<N>();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = cadd(mine[i], hbuf[((grp ^ 1) * 16 + i) * GE::G + g]);
+      // single-wave transforms exchange without barriers: keep the partner
+      // from overwriting the hand-over buffer before it has been read
+      if constexpr (GE::G == 64) __syncthreads();
+      inv_single<N, GE::P - 1>(x, xbuf, tw, grp, g);
+      if (r_own < K) add_lags<N>(part + (int64_t)r_own * M, x, M, g);
+    }
+    ++q;
+  }
+  finish_tile();
+}
+
 // Sums the partial ds windows of tiles split between workgroups; block b-1
 // handles the boundary between workgroups b-1 and b (the first boundary
-// inside a tile does the whole tile).
-template <int N>
+// inside a tile does the whole tile).  SEGS transforms per tile, K units per
+// tile (the filters, or the filter pairs of the paired adjoint).
+template <int N, int SEGS>
 __global__ void ols_ds_fixup_kernel(const float2* __restrict__ ws_ds, float2* __restrict__ ds, int64_t Ns, int K,
                                     int H, int64_t ntiles, int64_t P) {
-  using GE = Geo<N>;
   const int64_t b = (int64_t)blockIdx.x + 1;
   const int64_t U = ntiles * K;
   const int64_t ub = first_unit(U, P, b);
@@ -853,14 +1027,14 @@ __global__ void ols_ds_fixup_kernel(const float2* __restrict__ ws_ds, float2* __
   // blockIdx.y splits the window between workgroups: few outputs per lane,
   // so the lanes' loads are all in flight at once
   const int stride = blockDim.x * gridDim.y;
-  for (int sg = 0; sg < GE::SEGS; ++sg) {
-    const int64_t o0 = (t * GE::SEGS + sg) * H;
+  for (int sg = 0; sg < SEGS; ++sg) {
+    const int64_t o0 = (t * SEGS + sg) * H;
     for (int p = threadIdx.x + blockIdx.y * blockDim.x; p < H; p += stride) {
       if (o0 + p >= Ns) break;
       float2 a = make_float2(0.f, 0.f);
       for (int64_t bb = blo; bb <= bhi; ++bb) {
         const int64_t slot = bb == blo ? slot_lo : 0;
-        a = cadd(a, ws_ds[((bb * 2 + slot) * GE::SEGS + sg) * (int64_t)N + p]);
+        a = cadd(a, ws_ds[((bb * 2 + slot) * SEGS + sg) * (int64_t)N + p]);
       }
       ds[o0 + p] = a;
     }
@@ -1043,29 +1217,44 @@ struct Kern {
   static hipError_t occupancy(int nf, int flags, int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, forward_fn(nf, flags), GE::WG, 0);
   }
+  // The adjoint: paired segments up to N = 2048 (ols_backward_pair_kernel),
+  // one segment per group above.
+  // At N = 4096 a pair needs a 512-thread workgroup and 135 KB of LDS, one
+  // workgroup per CU: measured 7 % slower than the one-segment kernel there,
+  // 2-5 % faster at N = 512 .. 2048 (16 filters, 2^22 samples).
+  static constexpr bool PAIRED = N <= 2048;
+  static constexpr int BWD_SEGS = PAIRED ? BwdGeo<N>::SEGS : GE::SEGS;
+  static constexpr int BWD_WG = PAIRED ? BwdGeo<N>::WG : GE::WG;
+  using BwdFn = void (*)(const float2*, const float2*, int64_t, const float2*, int, int, int, int64_t, const float2*,
+                         float2*, float2*, float2*, int, int);
+  static BwdFn bwd_fn() {
+    if constexpr (PAIRED) return ols_backward_pair_kernel<N>;
+    else return ols_backward_kernel<N>;
+  }
   static hipError_t bwd_occupancy(int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, ols_backward_kernel<N>, GE::WG, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bwd_fn(), BWD_WG, 0);
   }
   static hipError_t backward(const ols_plan_s* p, const BwdWorkspace& w, const float2* s, const float2* gy,
                              int64_t Ns, float2* ds, float2* dh, hipStream_t st) {
     const int64_t nseg = (Ns + p->H - 1) / p->H;
-    const int64_t ntiles = (nseg + GE::SEGS - 1) / GE::SEGS;
-    const int64_t units = ntiles * p->K;
+    const int64_t ntiles = (nseg + BWD_SEGS - 1) / BWD_SEGS;
+    const int upt = PAIRED ? (p->K + 1) / 2 : p->K;  // units per tile
+    const int64_t units = ntiles * upt;
     const int64_t grid = units < w.grid ? units : w.grid;
-    hipLaunchKernelGGL(ols_backward_kernel<N>, dim3((unsigned)grid), dim3(GE::WG), 0, st, s, gy, Ns, p->spectra, p->K,
-                       p->M, p->H, ntiles, p->twiddles, ds, w.ws_ds, w.part_dh, ds ? 1 : 0, dh ? 1 : 0);
+    hipLaunchKernelGGL(bwd_fn(), dim3((unsigned)grid), dim3(BWD_WG), 0, st, s, gy, Ns, p->spectra, p->K, p->M, p->H,
+                       ntiles, p->twiddles, ds, w.ws_ds, w.part_dh, ds ? 1 : 0, dh ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ds && grid > 1) {
       // one workgroup per (tile boundary, eighth of the window): H <= 8192 outputs, at most 4 per lane
-      hipLaunchKernelGGL(ols_ds_fixup_kernel<N>, dim3((unsigned)(grid - 1), 8), dim3(256), 0, st, w.ws_ds, ds, Ns,
-                         p->K, p->H, ntiles, grid);
+      hipLaunchKernelGGL((ols_ds_fixup_kernel<N, BWD_SEGS>), dim3((unsigned)(grid - 1), 8), dim3(256), 0, st, w.ws_ds,
+                         ds, Ns, upt, p->H, ntiles, grid);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     if (dh) {
       const int64_t KM = (int64_t)p->K * p->M;
-      const int64_t nslots = grid * GE::SEGS, nch = dh_chunks(nslots);
+      const int64_t nslots = grid * BWD_SEGS, nch = dh_chunks(nslots);
       const unsigned bx = (unsigned)((KM + 255) / 256);
       hipLaunchKernelGGL(ols_dh_chunk_kernel, dim3(bx, (unsigned)nch), dim3(256), 0, st, w.part_dh, nslots, KM,
                          w.sum_dh);
@@ -1077,6 +1266,7 @@ struct Kern {
     return e;
   }
   static std::vector<float2> twiddles() { return build_twiddles<N>(); }
+  static int bwd_segs() { return BWD_SEGS; }
   static int block() { return GE::WG; }
   static int segs() { return GE::SEGS; }
 };
@@ -1127,6 +1317,10 @@ struct RunBackward {
 template <int N>
 struct RunTwiddles {
   static std::vector<float2> run() { return Kern<N>::twiddles(); }
+};
+template <int N>
+struct RunBwdSegs {
+  static int run() { return Kern<N>::bwd_segs(); }
 };
 template <int N>
 struct RunShape {
@@ -1529,14 +1723,14 @@ ols_status_t ols_plan_reserve_backward(ols_plan_t p) {
     int grid = 0;
     const ols_status_t r = bwd_full_grid(p, &grid);
     if (r != OLS_SUCCESS) return r;
-    const size_t bytes = bwd_ws_bytes(grid, p->segs, p->N, p->K, p->M).total();
+    const size_t bytes = bwd_ws_bytes(grid, dispatch<RunBwdSegs>(p->N), p->N, p->K, p->M).total();
     void* mem = nullptr;
     if (hipMalloc(&mem, bytes) != hipSuccess) {
       (void)hipGetLastError();
       return fail(OLS_ERROR_OUT_OF_MEMORY, "backward workspace");
     }
     p->bwd_mem = mem;
-    p->bwd = bwd_ws_carve(mem, grid, p->segs, p->N, p->K, p->M);
+    p->bwd = bwd_ws_carve(mem, grid, dispatch<RunBwdSegs>(p->N), p->N, p->K, p->M);
     return OLS_SUCCESS;
   } catch (...) {
     return fail(OLS_ERROR_INTERNAL, "exception in ols_plan_reserve_backward");
@@ -1579,16 +1773,16 @@ ols_status_t ols_backward_static(ols_plan_t p, const void* s, int64_t Ns, const 
     r = bwd_full_grid(p, &grid);
     if (r != OLS_SUCCESS) return r;
     // as many workgroups as the scratch holds, at most the full grid
-    const size_t one = bwd_ws_bytes(1, p->segs, p->N, p->K, p->M).total();
+    const size_t one = bwd_ws_bytes(1, dispatch<RunBwdSegs>(p->N), p->N, p->K, p->M).total();
     if (one > OLS_STATIC_SCRATCH_BYTES)
       return fail(OLS_ERROR_INVALID_VALUE,
                   "the adjoint of this plan needs " + std::to_string(one) + " bytes of scratch per workgroup, more than "
                   "the " + std::to_string((size_t)OLS_STATIC_SCRATCH_BYTES) + " bytes of ols_backward_static");
-    while (grid > 1 && bwd_ws_bytes(grid, p->segs, p->N, p->K, p->M).total() > OLS_STATIC_SCRATCH_BYTES) --grid;
+    while (grid > 1 && bwd_ws_bytes(grid, dispatch<RunBwdSegs>(p->N), p->N, p->K, p->M).total() > OLS_STATIC_SCRATCH_BYTES) --grid;
     void* base = nullptr;
     r = static_scratch_address(&base);
     if (r != OLS_SUCCESS) return r;
-    const BwdWorkspace w = bwd_ws_carve(base, grid, p->segs, p->N, p->K, p->M);
+    const BwdWorkspace w = bwd_ws_carve(base, grid, dispatch<RunBwdSegs>(p->N), p->N, p->K, p->M);
     e = dispatch<RunBackward>(p->N, (const ols_plan_s*)p, w, (const float2*)s, (const float2*)gy, Ns, (float2*)ds,
                               (float2*)dh, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");

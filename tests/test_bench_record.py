@@ -1,6 +1,7 @@
-"""Host-side checks of the benchmark's traffic record keying (no GPU): the
-device-code hash ignores comments and layout but not code, and a record taken
-on other code or another launch shape is not reported."""
+"""Host-side checks of the benchmark's profile record keying (no GPU): the
+device-code hash ignores comments and layout but not code, a record taken on
+other code or another launch shape is not reported, and the floors name the
+binding one."""
 
 import json
 import os
@@ -32,9 +33,19 @@ def test_traffic_record_needs_matching_code_and_launch(tmp_path, monkeypatch):
     h = bench.kernel_hash()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_hash", lambda: h)
-    assert bench.measured_traffic("test_workload", launch) == pytest.approx(123.0)
-    assert bench.measured_traffic("test_workload", dict(launch, grid=256)) is None
+    assert bench.profile_record("test_workload", launch)["hbm_bytes_per_launch"] == pytest.approx(123.0)
+    assert bench.profile_record("test_workload", dict(launch, grid=256)) is None
     rec["kernel_hash"] = "0" * 16
     path.write_text(json.dumps(rec))
-    assert bench.measured_traffic("test_workload", launch) is None
-    assert bench.measured_traffic("other_workload", launch) is None
+    assert bench.profile_record("test_workload", launch) is None
+    assert bench.profile_record("other_workload", launch) is None
+
+
+def test_floors_name_the_binding_one():
+    alg = 8e9  # 1 ms at 8 TB/s
+    assert bench.floors(alg, None) == {"hbm_ms": pytest.approx(1.0), "valu_ms": None,
+                                       "valu_instr_per_launch": None, "binding": "hbm"}
+    # 614.4e9 wave instructions per second: 1.2288e9 of them take 2 ms
+    f = bench.floors(alg, {"valu_instr_per_launch": 1.2288e9})
+    assert f["valu_ms"] == pytest.approx(2.0) and f["binding"] == "valu"
+    assert bench.floors(alg, {"valu_instr_per_launch": 1e8})["binding"] == "hbm"
