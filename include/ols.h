@@ -66,7 +66,8 @@ typedef enum {
  *   K      number of filters, >= 1
  *   M      filter length, 1 <= M <= N
  *   N      FFT length: power of two in [256, 8192], or 0 to let the library
- *          choose (cost model: FFT work per valid output sample)
+ *          choose (cost model: FFT work per valid output sample, among
+ *          N >= 1024; the shorter lengths run slower per output here)
  *   stream the filter spectra are computed on this stream; the plan may be
  *          used on any stream once this work is complete (the call itself
  *          synchronises `stream` before returning, so it is)
@@ -238,7 +239,8 @@ ols_status_t ols_plan_reserve_backward(ols_plan_t plan);
  *   h    device, complex64 [K][M]
  *   K, M >= 1
  *   N    FFT length of this item: power of two in [256, 4096], or 0 for the
- *        library's choice (cost model: least transform work per kept sample)
+ *        library's choice (cost model: least transform work per kept sample,
+ *        among N >= 1024)
  *   y    device, complex64 [K][N_s], must not overlap s; outputs of different
  *        items must not overlap each other (not checked)
  * Pointers must be 8-byte aligned.

@@ -380,14 +380,20 @@ OLS_HD int default_delay(int N, int M) {
 }
 
 // Cost model for N = 0: transform work per kept output sample, about
-// (K + 1) * 3.2 N log2 N + K * 4 N flops per segment over K * H kept samples.
-// Compared as exact integers (5x the work, cross-multiplied by the hops) so
-// that the host and the device pick the same N.  Returns 0 if no length in
-// [256, max_n] holds M taps.
+// (K + 1) * 3.2 N log2 N + K * 4 N flops per segment over K * H kept samples,
+// among N >= COST_MODEL_MIN_N.  Compared as exact integers (5x the work,
+// cross-multiplied by the hops) so that the host and the device pick the same
+// N.  N = 256 and 512 are left out: their transforms are narrower than a wave
+// and measured 10-24 % slower per output than N = 1024 on every cell of the
+// 2^25-sample sweep where both fit, although they need up to ~10 % fewer
+// flops (with them out, the model's N is within 6 % of the fastest measured
+// N in all 12 cells, against 24 % before).  Returns 0 if no length in
+// [COST_MODEL_MIN_N, max_n] holds M taps.
+constexpr int COST_MODEL_MIN_N = 1024;
 OLS_HD int cost_model_fft_length(int K, int M, int max_n) {
   int best = 0;
   unsigned __int128 best_w = 0, best_h = 1;
-  for (int n = 256; n <= max_n; n *= 2) {
+  for (int n = COST_MODEL_MIN_N; n <= max_n; n *= 2) {
     if (n < M) continue;
     const int h = n - default_delay(n, M);
     if (h < 1) continue;
