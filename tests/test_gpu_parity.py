@@ -16,7 +16,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import conv  # noqa: E402
+from oracle import conv, post  # noqa: E402
 import workloads  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -273,6 +273,44 @@ def test_filter_bank_off_grid_rows_sampled(ols, extra):
     rel, n = sampled_check(ols, wl, windows=8)
     say(f"  filter_bank 2^23+{extra}: {n} sampled outputs per row, max rel L2 {rel.max():.3e}")
     assert np.all(rel <= TOL), rel
+
+
+ROW_PHASE_CASES = [
+    # (Ns, K, M, N, derivative)
+    (20001, 3, 256, 2048, False),
+    (20003, 3, 250, 2048, False),
+    (9999, 5, 40, 256, False),      # transforms narrower than a wave (per-lane stores)
+    (30001, 2, 100, 1024, False),   # one wave per transform
+    (40005, 4, 513, 4096, False),
+    (7001, 2, 1000, 1024, False),   # D = 1008, H = 16
+    (25001, 3, 255, 2048, True),    # derivative (effective M = 256)
+    (5, 2, 7, 256, False),          # a single segment, shorter than a granule
+]
+
+
+@pytest.mark.parametrize("Ns,K,M,N,deriv", ROW_PHASE_CASES)
+@pytest.mark.parametrize("phase", [1, 3, 7])
+def test_row_phase_aligned_boundaries_full(ols, Ns, K, M, N, deriv, phase):
+    """Output rows that start off the 64-byte grid, at several granule
+    phases: part of every store goes through the default-policy branch of the
+    granule-aware store.  y starts `phase` samples past a granule boundary of
+    a NaN-filled buffer; every output and both guard bands are checked."""
+    say(f"row phase {phase}: Ns={Ns} K={K} M={M} N={N} deriv={deriv}")
+    s, h = workloads.make_signal_filters(Ns, K, M, seed=Ns + phase)
+    plan = ols.OLSPlan(dev(h), N=N, derivative=deriv)
+    buf = torch.full((K * Ns + 2 * GUARD,), complex(float("nan"), float("nan")), dtype=torch.complex64, device="cuda")
+    assert buf.data_ptr() % 64 == 0
+    y = buf[GUARD + phase:GUARD + phase + K * Ns].view(K, Ns)
+    plan.forward(dev(s), y)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(buf[:GUARD + phase].real).all()), "guard before y written"
+    assert bool(torch.isnan(buf[GUARD + phase + K * Ns:].real).all()), "guard after y written"
+    got = y.cpu().numpy()
+    assert not np.isnan(got).any(), "output not written everywhere"
+    ref = post.conv_derivative(s, h) if deriv else conv.direct_conv(s, h)
+    rel = rel_rows(got, ref)
+    assert np.all(rel <= TOL), rel
+    plan.close()
 
 
 def test_filter_bank_2p23_prefix_full(ols):
