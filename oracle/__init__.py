@@ -29,7 +29,9 @@ the Overlap-and-Save Method in Shared Memory"):
 * ``adjoint``              -- the adjoint (gradient) of eq. (1) with respect to
   the signal and to the filters, by direct correlation.
 * ``post``                 -- post-processing of the output (sec. 4): the
-  power |y|^2 and the numerical derivative (backward difference).
+  power |y|^2, the numerical derivative (backward difference) and the
+  non-local polyphase stencil (derivative, Lagrange interpolation) applied to
+  eq. (1)'s output and its tail.
 
 Every function is pinned by tests in ``tests/test_oracle*.py`` against things
 other than itself: hand-derived fixtures under ``tests/golden/``, closed forms

@@ -334,6 +334,84 @@ def pin_derivative_closed_forms(derivative, conv):
     _close(derivative(conv(s, h)), want, 1e-13, "delta")
 
 
+# ------------------------------------------------------- non-local stencil
+
+def pin_stencil_golden(stencil, conv_stencil):
+    """Hand-worked fixture: cubic midpoint interpolation, backward and central
+    differences on a given sequence, and interpolation of a convolution whose
+    tail (samples past N_s) the stencil reads."""
+    d = load_golden("stencil_small.json")
+    y = _c(d, "y_re", "y_im")
+    w = np.asarray(d["interp_w"], dtype=np.float64)
+    L = d["interp_left"]
+    _close(stencil(y, w, L, 4), _c(d, "interp_re", "interp_im"), 1e-14, "stencil_small interp")
+    _close(stencil(y[:4], np.array([[-1.0, 1.0]]), 1, 4), _c(d, "diff_re", "diff_im"), 1e-14, "stencil_small diff")
+    _close(stencil(y[:5], np.array([[-0.5, 0.0, 0.5]]), 1, 4), _c(d, "central_re", "central_im"), 1e-14,
+           "stencil_small central")
+    s = _c(d, "s_re", "s_im")
+    h = _c(d, "h_re", "h_im")
+    _close(conv_stencil(s, h, w, L), _c(d, "conv_interp_re", "conv_interp_im"), 1e-14, "stencil_small conv interp")
+
+
+def pin_stencil_closed_forms(stencil, derivative):
+    rng = np.random.default_rng(41)
+    Ns = 60
+    # identity stencil
+    y = rand_c(rng, 2, Ns)
+    _close(stencil(y, np.array([[1.0]]), 0, Ns), y, 1e-15, "identity")
+    # the backward-difference stencil is the (separately pinned) derivative
+    _close(stencil(y, np.array([[-1.0, 1.0]]), 1, Ns), derivative(y), 1e-14, "difference = derivative")
+    # impulse response: y = delta at m gives z[J n + j] = w[j][m - n + L] for the n it reaches
+    J, L, R = 3, 2, 1
+    w = rng.uniform(-1, 1, (J, L + 1 + R))
+    m = 30
+    yd = np.zeros(Ns + R, dtype=complex)
+    yd[m] = 1
+    want = np.zeros(J * Ns, dtype=complex)
+    for n in range(m - R, m + L + 1):
+        for j in range(J):
+            want[J * n + j] = w[j, m - n + L]
+    _close(stencil(yd, w, L, Ns), want, 1e-15, "impulse response")
+    # complex exponential: z[J n + j] = e^{i a n} sum_d w[j][d + L] e^{i a d} once every tap is at n + d >= 0
+    a = 0.41
+    ye = np.exp(1j * a * np.arange(Ns + R))
+    resp = np.array([sum(w[j, d + L] * np.exp(1j * a * d) for d in range(-L, R + 1)) for j in range(J)])
+    ze = stencil(ye, w, L, Ns).reshape(Ns, J)
+    _close(ze[L:], np.exp(1j * a * np.arange(L, Ns))[:, None] * resp[None, :], 1e-13, "exponential response")
+    # zero history: the first outputs drop the taps before sample 0
+    _close(ze[0], [w[j, L:] @ ye[: R + 1] for j in range(J)], 1e-13, "zero history")
+    # Lagrange midpoint weights reproduce a cubic exactly, phase 0 returns the samples
+    c = rand_c(rng, 4)
+    t = np.arange(Ns + 2, dtype=float)
+    yp = c[0] + c[1] * t + c[2] * t**2 + c[3] * t**3
+    wi = np.array([[0, 1, 0, 0], [-1 / 16, 9 / 16, 9 / 16, -1 / 16]])
+    zi = stencil(yp, wi, 1, Ns).reshape(Ns, 2)
+    tm = t[1:Ns] + 0.5
+    _close(zi[1:, 1], c[0] + c[1] * tm + c[2] * tm**2 + c[3] * tm**3, 1e-11, "cubic midpoint exact")
+    _close(zi[:, 0], yp[:Ns], 1e-15, "phase 0")
+
+
+def pin_lagrange(lagrange_weights, midpoint_stencil):
+    # the textbook cubic midpoint weights (derived by hand in stencil_small.json)
+    _close(lagrange_weights([-1, 0, 1, 2], 0.5), np.array([-1, 9, 9, -1]) / 16, 1e-15, "cubic midpoint weights")
+    # at a node the weights pick that sample
+    _close(lagrange_weights([-2, -1, 0, 1, 2], 1.0), [0, 0, 0, 1, 0], 1e-15, "node")
+    # exact for every power x^k, k < T, at any offset
+    rng = np.random.default_rng(42)
+    nodes = np.array([-3, -1, 0, 2, 5], dtype=float)
+    for x in rng.uniform(-3, 5, 4):
+        wts = lagrange_weights(nodes, x)
+        for k in range(nodes.shape[0]):
+            _close(wts @ nodes**k, x**k, 1e-10, f"x^{k} at {x:.3f}")
+    w, L = midpoint_stencil(1, 2)
+    assert L == 1 and w.shape == (2, 4)
+    _close(w[0], [0, 1, 0, 0], 0, "midpoint phase 0")
+    _close(w[1], np.array([-1, 9, 9, -1]) / 16, 1e-15, "midpoint phase 1")
+    # linear interpolation through offsets 0, 1
+    w, L = midpoint_stencil(0, 1)
+    _close(w, [[1, 0], [0.5, 0.5]], 1e-15, "linear midpoint")
+
+
 # ------------------------------------------------------------------ R2R
 
 def pin_real_conv(conv_real):

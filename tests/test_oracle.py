@@ -231,6 +231,38 @@ def test_post_composed_and_sampled():
     P._close(post.derivative_at(s, h, idx), post.derivative(y)[:, idx], 1e-12, "derivative_at")
 
 
+def test_stencil_pins():
+    P.pin_stencil_golden(post.stencil, post.conv_stencil)
+    P.pin_stencil_closed_forms(post.stencil, post.derivative)
+    P.pin_lagrange(post.lagrange_weights, post.midpoint_interpolation_stencil)
+
+
+def test_stencil_composed_and_sampled():
+    rng = np.random.default_rng(43)
+    s = P.rand_c(rng, 2000)
+    h = P.rand_c(rng, 3, 40)
+    w, L = post.midpoint_interpolation_stencil()
+    z = post.conv_stencil(s, h, w, L)
+    assert z.shape == (3, 4000)
+    # the stencil of the convolution continued by zeros, by hand
+    y = conv.direct_conv(np.concatenate([s, np.zeros(2)]), h)
+    P._close(z, post.stencil(y, w, L, 2000), 1e-14, "conv_stencil")
+    # phase 0 is eq. (1); the backward difference is the derivative
+    P._close(z[:, 0::2], conv.direct_conv(s, h), 1e-12, "phase 0")
+    P._close(post.conv_stencil(s, h, [[-1.0, 1.0]], 1), post.conv_derivative(s, h), 1e-12, "difference")
+    idx = np.array([0, 1, 2, 3, 78, 79, 80, 81, 1234, 3997, 3998, 3999])
+    P._close(post.stencil_at(s, h, w, L, idx), z[:, idx], 1e-12, "stencil_at")
+    with pytest.raises(IndexError):
+        post.stencil_at(s, h, w, L, [4000])
+    # R2R: the real stencil of the real convolution
+    sr = rng.uniform(-1, 1, 1500)
+    hr = rng.uniform(-1, 1, (2, 33))
+    zr = post.conv_stencil_real(sr, hr, w, L)
+    yr = conv.direct_conv_real(np.concatenate([sr, np.zeros(2)]), hr)
+    P._close(zr, post.stencil(yr, w, L, 1500).real, 1e-14, "conv_stencil_real")
+    P._close(post.stencil_at(sr, hr, w, L, idx[:-3], real=True), zr[:, idx[:-3]], 1e-12, "stencil_at real")
+
+
 def test_real_conv_pins():
     P.pin_real_conv(conv.direct_conv_real)
 

@@ -243,3 +243,80 @@ def _real_no_history(s, h):
 @pytest.mark.parametrize("mutant", [_real_corr, _real_no_history])
 def test_real_conv_mutants_fail(mutant):
     assert _fails(P.pin_real_conv, mutant)
+
+
+# ---------------------------------------------------------- stencil mutants
+
+def _stencil_mutant(flip_d=False, transpose_phases=False, shift_tap=0, wrap_history=False):
+    def stencil(y, w, left, Ns):
+        y = np.asarray(y, dtype=np.complex128)
+        w = np.atleast_2d(np.asarray(w, dtype=np.float64))
+        J, T = w.shape
+        right = T - 1 - left
+        z = np.zeros(y.shape[:-1] + (Ns, J), dtype=np.complex128)
+        for j in range(J):
+            for d in range(-left, right + 1):
+                dd = -d if flip_d else d + shift_tap
+                for n in range(Ns):
+                    m = n + dd
+                    if m < 0 and not wrap_history:
+                        continue
+                    if m >= y.shape[-1]:
+                        continue
+                    z[..., n, j] += w[j, d + left] * y[..., m]
+        if transpose_phases:
+            return np.moveaxis(z, -1, -2).reshape(y.shape[:-1] + (J * Ns,))
+        return z.reshape(y.shape[:-1] + (J * Ns,))
+    return stencil
+
+
+def _conv_stencil_with(stencil, zero_tail=False):
+    def conv_stencil(s, h, w, left):
+        s = np.asarray(s, dtype=np.complex128).ravel()
+        R = np.atleast_2d(w).shape[1] - 1 - left
+        if zero_tail:
+            y = conv.direct_conv(s, h)
+            y = np.concatenate([y, np.zeros((y.shape[0], R))], axis=1)
+        else:
+            y = conv.direct_conv(np.concatenate([s, np.zeros(R)]), h)
+        return stencil(y, w, left, s.shape[0])
+    return conv_stencil
+
+
+@pytest.mark.parametrize("kw", [dict(flip_d=True), dict(transpose_phases=True), dict(shift_tap=1),
+                                dict(shift_tap=-1), dict(wrap_history=True)])
+def test_stencil_mutants_fail(kw):
+    from oracle import post
+    m = _stencil_mutant(**kw)
+    assert (_fails(P.pin_stencil_golden, m, _conv_stencil_with(m))
+            or _fails(P.pin_stencil_closed_forms, m, post.derivative))
+
+
+def test_stencil_zero_tail_mutant_fails():
+    from oracle import post
+    assert _fails(P.pin_stencil_golden, post.stencil, _conv_stencil_with(post.stencil, zero_tail=True))
+
+
+def test_unmutated_stencil_copy_passes():
+    from oracle import post
+    m = _stencil_mutant()
+    P.pin_stencil_golden(m, _conv_stencil_with(m))
+    P.pin_stencil_closed_forms(m, post.derivative)
+
+
+def _lagrange_mutant(swap=False, skip_last=False):
+    def weights(nodes, x):
+        t = np.asarray(nodes, dtype=np.float64)
+        out = np.ones(t.shape[0])
+        for k in range(t.shape[0]):
+            for i in range(t.shape[0] - (1 if skip_last else 0)):
+                if i != k:
+                    out[k] *= (x - t[i]) / ((t[i] - t[k]) if swap else (t[k] - t[i]))
+        return out
+    return weights
+
+
+@pytest.mark.parametrize("kw", [dict(swap=True), dict(skip_last=True)])
+def test_lagrange_mutants_fail(kw):
+    from oracle import post
+    assert _fails(P.pin_lagrange, _lagrange_mutant(**kw), post.midpoint_interpolation_stencil)
