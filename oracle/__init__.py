@@ -30,8 +30,8 @@ the Overlap-and-Save Method in Shared Memory"):
   the signal and to the filters, by direct correlation.
 * ``post``                 -- post-processing of the output (sec. 4): the
   power |y|^2, the numerical derivative (backward difference) and the
-  non-local polyphase stencil (derivative, Lagrange interpolation) applied to
-  eq. (1)'s output and its tail.
+  non-local stencil with J outputs per sample (derivative, Lagrange
+  interpolation) applied to eq. (1)'s output and its tail.
 
 Every function is pinned by tests in ``tests/test_oracle*.py`` against things
 other than itself: hand-derived fixtures under ``tests/golden/``, closed forms

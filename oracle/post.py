@@ -11,8 +11,8 @@ the paper names the operation but not its formula:
   zero history of eq. (1), d_r[n] = y_r[n] - y_r[n-1], y_r[-1] = 0.  It is
   causal, so it needs only samples the segment already holds.
 * stencil: the general neighbourhood operation of sec. 4 (its examples: the
-  derivative and interpolation) read as a polyphase stencil with real weights.
-  Each output sample n yields J values
+  derivative and interpolation) read as a stencil with real weights and J
+  outputs (phases) per sample: each output sample n yields J values
       z_r[J n + j] = sum_{d=-L}^{R} w[j][d + L] * y_r[n + d],   n = 0 .. N_s - 1,
   so a row of z has J * N_s samples.  y_r[m] = 0 for m < 0 (zero history of
   eq. (1)); for m >= N_s, y_r[m] is eq. (1) of the signal continued by zeros
