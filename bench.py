@@ -346,8 +346,9 @@ def fwd_bwd_measurement(steps: int, warmup: int) -> dict:
 
 
 def variants_measurement(steps: int, warmup: int) -> dict:
-    """The fused post-processing options (power, derivative) on the benchmark
-    filter bank, and the real-to-real path on the same shape with real data,
+    """The fused post-processing options (power, derivative, the non-local
+    stencil stage) on the benchmark filter bank, and the real-to-real path on
+    the same shape with real data,
     each timed with HIP events on the launch stream; bytes are the algorithmic
     HBM bytes of each variant (signal + outputs + taps)."""
     import numpy as np
@@ -374,13 +375,23 @@ def variants_measurement(steps: int, warmup: int) -> dict:
     wl = workloads.WORKLOADS["filter_bank_2p23_k32_m256"]
     s_np, h_np = workloads.make_signal_filters(wl.Ns, wl.K, wl.M, seed=wl.seed)
     s, h = torch.from_numpy(s_np).cuda(), torch.from_numpy(h_np).cuda()
-    for name, kw, ybytes in (("power", {"power": True}, 4), ("derivative", {"derivative": True}, 8)):
+    # the non-local stage (sec. 4): the backward difference from neighbouring
+    # outputs (J = 1; the same result as the folded derivative above), the
+    # cubic midpoint interpolation (J = 2 outputs per sample) and its power
+    difference = ([[-1.0, 1.0]], 1)
+    cubic = ([[0.0, 1.0, 0.0, 0.0], [-1.0 / 16, 9.0 / 16, 9.0 / 16, -1.0 / 16]], 1)
+    for name, kw, ybytes in (("power", {"power": True}, 4), ("derivative", {"derivative": True}, 8),
+                             ("stage_difference", {"stencil": difference}, 8),
+                             ("stage_midpoint_cubic", {"stencil": cubic}, 8),
+                             ("stage_midpoint_cubic_power", {"stencil": cubic, "power": True}, 4)):
         plan = OLSPlan(h, N=wl.N, **kw)
-        y = torch.empty((wl.K, wl.Ns), dtype=torch.float32 if ybytes == 4 else torch.complex64, device="cuda")
+        J = plan.phases
+        y = torch.empty((wl.K, J * wl.Ns), dtype=torch.float32 if ybytes == 4 else torch.complex64, device="cuda")
         ms = timed(lambda: plan.forward(s, y))
-        alg = ybytes * wl.K * wl.Ns + 8 * wl.Ns + 8 * wl.K * wl.M
+        alg = ybytes * J * wl.K * wl.Ns + 8 * wl.Ns + 8 * wl.K * wl.M
         out[name] = {"workload": wl.name, "ms": ms, "samples_per_s": wl.K * wl.Ns / (ms * 1e-3),
-                     "alg_GBps": alg / (ms * 1e-3) / 1e9}
+                     "outputs_per_sample": J, "alg_GBps": alg / (ms * 1e-3) / 1e9,
+                     "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         plan.close()
         del y
     del s, h

@@ -127,9 +127,45 @@ ols_status_t ols_plan_update_filters(ols_plan_t plan, const void* h, ols_stream_
  * 1 <= H <= N - M + 1 gives the same output.  By default the library uses the
  * largest H whose segments start on 16-sample (128-byte) boundaries:
  * D = M - 1 rounded up to a multiple of 16 (when that still leaves room),
- * H = N - D.  H = 0 restores the default.  Errors: INVALID_VALUE.
+ * H = N - D.  H = 0 restores the default.  With a stencil (below) the limit is
+ * 1 <= H <= N - (M - 1 + left) - right.  Errors: INVALID_VALUE.
  */
 ols_status_t ols_plan_set_hop(ols_plan_t plan, int32_t H);
+
+/*
+ * ols_plan_set_stencil -- non-local post-processing inside the forward kernel
+ * (sec. 4: an output combined with its neighbours, the paper's examples being
+ * the numerical derivative and interpolation).  After each segment's inverse
+ * FFT its outputs are staged in LDS, and every output sample n of filter r
+ * yields J values
+ *     z_r[J*n + j] = sum_{d=-left}^{right} w[j*T + d + left] * y_r[n + d],
+ *     T = left + 1 + right, j = 0 .. J-1,
+ * with y_r[m] = 0 for m < 0 (zero history) and, for m >= N_s, y_r[m] the
+ * convolution of the signal continued by zeros (its tail).  The plan's other
+ * flags apply around it: OLS_POST_DERIVATIVE before (y is then the
+ * derivative), OLS_POST_POWER after (|z|^2, float32), OLS_REAL throughout
+ * (float32 rows).  ols_forward then writes y as [K][J*N_s] elements of the
+ * plan's output type.  Example, cubic midpoint interpolation (two outputs per
+ * sample): J = 2, left = 1, right = 2, w = {0, 1, 0, 0, -1/16, 9/16, 9/16,
+ * -1/16}.
+ *   J       phases, 1 .. 4; 0 removes the stencil (left, right, w ignored).
+ *   left    taps before the sample, right taps after: left, right >= 0,
+ *           left + 1 + right <= 8.
+ *   w       host array of J*T float32 weights, read during the call only.
+ * Each segment keeps only outputs whose neighbours are unaliased: the first
+ * kept position D >= M - 1 + left (M + 1 with the derivative) and the hop
+ * H <= N - D - right, so M - 1 + left + right <= N - 1 is required; the
+ * default hop is N - D - right rounded down to a multiple of 16 samples (when
+ * at least 16), which keeps segments on the 128-byte output grid.  The call
+ * resets the hop to that default and the tiling to one filter per unit and
+ * the stage kernel's occupancy (ols_plan_set_tiling may change it after).
+ * With y aligned to J output elements (always for J = 1), one or two phases
+ * per sample are written as one element.  A plan with a stencil has no
+ * ols_backward (UNSUPPORTED).
+ * Errors: INVALID_VALUE (null plan or w, J, left, right out of range, filter
+ * too long for the stencil), HIP.
+ */
+ols_status_t ols_plan_set_stencil(ols_plan_t plan, int32_t J, int32_t left, int32_t right, const float* w);
 
 /* Plan properties: FFT length N, hop H, delay D (first kept circular sample,
  * D >= M - 1), K and M.  Any output pointer may be NULL. */

@@ -35,6 +35,7 @@ SIGNATURES = {
     "ols_plan_ex": (_I32, [ctypes.POINTER(_P), _P, _I32, _I32, _I32, _I32, _P]),
     "ols_plan_update_filters": (_I32, [_P, _P, _P]),
     "ols_plan_set_hop": (_I32, [_P, _I32]),
+    "ols_plan_set_stencil": (_I32, [_P, _I32, _I32, _I32, _P]),
     "ols_plan_get_info": (_I32, [_P, _PI32, _PI32, _PI32, _PI32, _PI32]),
     "ols_plan_get_spectra": (_I32, [_P, _P, _P]),
     "ols_plan_get_launch": (_I32, [_P, _PI32, _PI32, _PI32]),

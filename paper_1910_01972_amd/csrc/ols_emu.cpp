@@ -153,7 +153,7 @@ std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<flo
 template <int N>
 void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int K, int D, int H, int64_t u0,
                    int64_t u1, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw, int NF = 1,
-                   bool power = false, bool real = false) {
+                   bool power = false, bool real = false, const Stencil* st = nullptr) {
   using GE = Geo<N>;
   const int KG = (K + NF - 1) / NF;
   std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
@@ -189,6 +189,25 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
       }
       exchange_phase<N, GE::P - 2, GE::P - 1, GE::P - 2>(xs, G);
       inv_from<N, GE::P - 2>(xs, G, tw);
+      if (st) {
+        // the non-local stage: each segment's outputs staged in slots that
+        // start as NaN, so a kept output that read an unstaged slot shows up
+        const int64_t row = (int64_t)r * st->J * Ns;
+        for (int grp = 0; grp < GE::SEGS; ++grp) {
+          std::vector<float2> region(stage_stride<N>(), make_float2(NAN, NAN));
+          for (int g = 0; g < GE::G; ++g)
+            stage_write<N>(region.data(), *reinterpret_cast<const float2(*)[16]>(xs[grp * GE::G + g].data()), g);
+          const int64_t seg = tile * GE::SEGS + grp;
+          float* yr = reinterpret_cast<float*>(y) + row;
+          for (int g = 0; g < GE::G; ++g) {
+            if (real && power) stage_store<N, true, true>(region.data(), *st, yr, Ns, seg * 2 * H, D, H, g);
+            else if (real) stage_store<N, false, true>(region.data(), *st, yr, Ns, seg * 2 * H, D, H, g);
+            else if (power) stage_store<N, true, false>(region.data(), *st, yr, Ns, seg * H, D, H, g);
+            else stage_store<N, false, false>(region.data(), *st, y + row, Ns, seg * H, D, H, g);
+          }
+        }
+        continue;
+      }
       for (int t = 0; t < GE::WG; ++t) {
         const int grp = t / GE::G, g = t % GE::G;
         const int64_t seg = tile * GE::SEGS + grp;
@@ -206,7 +225,7 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
 
 template <int N>
 int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y,
-            int post = 0) {
+            int post = 0, const Stencil* st = nullptr) {
   using GE = Geo<N>;
   const std::vector<float2> table = build_twiddles<N>();
   bool guards = true;
@@ -224,7 +243,7 @@ int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, i
   G.poison();
   for (int b = 0; b < grid; ++b) {
     const int64_t u0 = first_unit(U, grid, b), u1 = first_unit(U, grid, b + 1);
-    if (u0 < u1) forward_range<N>(s, Ns, F.data(), y, K, D, H, u0, u1, G, tw, nf, (post & 2) != 0, real);
+    if (u0 < u1) forward_range<N>(s, Ns, F.data(), y, K, D, H, u0, u1, G, tw, nf, (post & 2) != 0, real, st);
   }
   return G.guards_ok() ? 0 : 3;
 }
@@ -454,8 +473,8 @@ int dispatch(int N, A... a) {
 template <int N>
 struct RunFwd {
   static int run(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y,
-                 int post) {
-    return forward<N>(s, Ns, h, K, M, D, H, grid, y, post);
+                 int post, const Stencil* st) {
+    return forward<N>(s, Ns, h, K, M, D, H, grid, y, post, st);
   }
 };
 template <int N>
@@ -538,7 +557,7 @@ extern "C" {
 // an unsupported N.
 int ols_emu_forward(int N, const float* s, int64_t Ns, const float* h, int K, int M, int D, int H, int grid, float* y) {
   return ols::emu::dispatch<ols::emu::RunFwd>(N, (const float2*)s, Ns, (const float2*)h, K, M, D, H, grid, (float2*)y,
-                                              0);
+                                              0, (const ols::Stencil*)nullptr);
 }
 
 // As ols_emu_forward with the flags of ols_plan_ex (1: first difference folded
@@ -547,8 +566,34 @@ int ols_emu_forward(int N, const float* s, int64_t Ns, const float* h, int K, in
 int ols_emu_forward_post(int N, const float* s, int64_t Ns, const float* h, int K, int M, int D, int H, int grid,
                          int post, float* y) {
   return ols::emu::dispatch<ols::emu::RunFwd>(N, (const float2*)s, Ns, (const float2*)h, K, M, D, H, grid, (float2*)y,
-                                              post);
+                                              post, (const ols::Stencil*)nullptr);
 }
+
+// As ols_emu_forward_post with the non-local stencil stage (J phases, left
+// and right reach, weights w[J][left + 1 + right]); y holds [K][J*Ns] outputs.
+// packed = 1 takes the packed store form where the library would (J <= 2, y
+// aligned to J elements), 0 never.  Returns 1 for an invalid stencil.
+int ols_emu_forward_stencil(int N, const float* s, int64_t Ns, const float* h, int K, int M, int D, int H, int grid,
+                            int post, int J, int L, int R, const float* w, int packed, float* y) {
+  if (J < 1 || J > ols::STENCIL_MAX_PHASES || L < 0 || R < 0 || L + 1 + R > ols::STENCIL_MAX_TAPS) return 1;
+  ols::Stencil st{};
+  const uintptr_t el = (uintptr_t)J * ((post & 6) ? 4 : 8);
+  st.packed = packed && J <= 2 && (uintptr_t)y % el == 0;
+  st.J = J;
+  st.L = L;
+  st.T = L + 1 + R;
+  for (int j = 0; j < J; ++j)
+    for (int d = 0; d < st.T; ++d) st.w[j][d] = w[j * st.T + d];
+  return ols::emu::dispatch<ols::emu::RunFwd>(N, (const float2*)s, Ns, (const float2*)h, K, M, D, H, grid, (float2*)y,
+                                              post, (const ols::Stencil*)&st);
+}
+
+// First kept position of a plan with a stencil reaching L back and R ahead
+// (the host plan code's rule; the hop is N - D - R).
+int ols_emu_stencil_delay(int N, int Meff, int L, int R) { return ols::stencil_delay(N, Meff, L, R); }
+
+// Default hop of such a plan.
+int ols_emu_stencil_hop(int N, int D, int R) { return ols::stencil_hop(N, D, R); }
 
 // Adjoint through the kernel dataflow: ds[N_s], dh[K][M].
 int ols_emu_backward(int N, const float* s, int64_t Ns, const float* gy, const float* h, int K, int M, int D, int H,

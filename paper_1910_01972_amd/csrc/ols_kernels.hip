@@ -202,12 +202,25 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
 template <int N, int NF>
 constexpr bool prefetch_spectra() { return NF == 1 && N != 1024; }
 
+// Exchange buffers of a forward kernel (double-buffered only across waves),
+// and its LDS: the buffers, plus, for the non-local stage with transforms no
+// wider than a wave, one wave-private set of stage slots per transform (wider
+// transforms stage in an exchange buffer, under the exchanges' barriers).
+template <int N, int NF>
+constexpr int forward_bufs() { return (NF == 1 && Geo<N>::G > 64) ? 2 : NF; }
+template <int N, int NF, bool STAGE>
+constexpr int forward_lds() {
+  return forward_bufs<N, NF>() * Geo<N>::LDS + ((STAGE && Geo<N>::G <= 64) ? Geo<N>::SEGS * stage_stride<N>() : 0);
+}
+
+// STAGE: the outputs go through the non-local stencil stage (st) instead of
+// the plain store; the output rows then hold st->J * N_s elements.
 template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE,
-          bool PF = prefetch_spectra<N, NF>()>
+          bool PF = prefetch_spectra<N, NF>(), bool STAGE = false>
 __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2 (&tw)[Geo<N>::TWR], int64_t u0, int64_t u1, float2* lds,
-                                              int& par) {
+                                              int& par, const Stencil* st = nullptr) {
   using GE = Geo<N>;
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
@@ -248,7 +261,55 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
       load_spectrum<N>(x[f], Fg, r < K ? r : K - 1, g);
     }
   };
+  // stencil phases of filter r's segment (pair) sg, staged at region
+  auto stage_out = [&](const float2* region, int r, int64_t sg) {
+    const int64_t row = (int64_t)r * st->J * Ns;
+    if constexpr (REAL) stage_store<N, POWER, true, SMODE>(region, *st, y_r + row, Ns, sg * step, D, H, g);
+    else if constexpr (POWER) stage_store<N, true, false, SMODE>(region, *st, y_r + row, Ns, sg * H, D, H, g);
+    else stage_store<N, false, false, SMODE>(region, *st, y_c + row, Ns, sg * H, D, H, g);
+  };
+  auto stage_group = [&](const float2 (&x)[NF][16], int q, int64_t sg) {
+    if constexpr (GE::G <= 64) {
+      // a transform lies in one wave, whose LDS operations complete in order:
+      // its own stage slots need fences against compiler reordering only
+      float2* region = lds + forward_bufs<N, NF>() * GE::LDS + grp * stage_stride<N>();
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        stage_write<N>(region, x[f], g);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int r = q * NF + f;
+        if (NF == 1 || r < K) stage_out(region, r, sg);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+    } else {
+      static_assert(GE::SEGS * stage_stride<N>() <= GE::LDS, "stage slots fit in an exchange buffer");
+      if constexpr (NF == 1) {
+        // one more exchange of the two-buffer sequence (see exchange)
+        float2* region = lds + (par ? GE::LDS : 0) + grp * stage_stride<N>();
+        par ^= 1;
+        stage_write<N>(region, x[0], g);
+        __syncthreads();
+        stage_out(region, q, sg);
+      } else {
+        // as exchange_nf: one buffer per filter, a barrier after the writes
+        // and one after the reads
+#pragma unroll
+        for (int f = 0; f < NF; ++f) stage_write<N>(lds + f * GE::LDS + grp * stage_stride<N>(), x[f], g);
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const int r = q * NF + f;
+          if (r < K) stage_out(lds + f * GE::LDS + grp * stage_stride<N>(), r, sg);
+        }
+        __syncthreads();
+      }
+    }
+  };
   auto store_group = [&](const float2 (&x)[NF][16], int q, int64_t sg) {
+    if constexpr (STAGE) {
+      stage_group(x, q, sg);
+      return;
+    }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const int r = q * NF + f;
@@ -304,14 +365,16 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
   }
 }
 
-template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE>
+template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE, bool STAGE = false>
 __device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2* __restrict__ twt, int64_t u0, int64_t u1, float2* lds,
-                                              int& par) {
+                                              int& par, const Stencil* st = nullptr) {
   float2 tw[Geo<N>::TWR];
   load_lane_twiddles<N>(tw, twt, threadIdx.x % Geo<N>::G);
-  forward_units<N, NF, POWER, REAL, SMODE>(sv, Ns, F, yv, K, D, H, tw, u0, u1, lds, par);
+  // the stage's accumulators take the registers of the spectrum prefetch
+  forward_units<N, NF, POWER, REAL, SMODE, prefetch_spectra<N, NF>() && !STAGE, STAGE>(sv, Ns, F, yv, K, D, H, tw, u0,
+                                                                                        u1, lds, par, st);
 }
 
 template <int N, int NF, bool POWER, bool REAL>
@@ -319,15 +382,31 @@ __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const void* __r
                                                                  const float2* __restrict__ F, void* __restrict__ y,
                                                                  int K, int D, int H, int64_t ntiles,
                                                                  const float2* __restrict__ twt) {
-  using GE = Geo<N>;
-  constexpr int BUFS = (NF == 1 && GE::G > 64) ? 2 : NF;  // double-buffered only across waves
-  __shared__ float2 lds[BUFS * GE::LDS];
+  __shared__ float2 lds[forward_lds<N, NF, false>()];
   const int64_t U = ntiles * ((K + NF - 1) / NF);
   const int64_t u0 = first_unit(U, gridDim.x, blockIdx.x);
   const int64_t u1 = first_unit(U, gridDim.x, blockIdx.x + 1);
   if (u0 >= u1) return;  // uniform over the workgroup
   int par = 0;
   forward_range<N, NF, POWER, REAL>(s, Ns, F, y, K, D, H, twt, u0, u1, lds, par);
+}
+
+// The forward kernel with the non-local post-processing stage (sec. 4): the
+// same units, each filter's output staged in LDS and stored as st's phases.
+template <int N, int NF, bool POWER, bool REAL>
+__global__ __launch_bounds__(Geo<N>::WG) __attribute__((amdgpu_waves_per_eu(2))) void ols_forward_stencil_kernel(const void* __restrict__ s, int64_t Ns,
+                                                                         const float2* __restrict__ F,
+                                                                         void* __restrict__ y, int K, int D, int H,
+                                                                         int64_t ntiles,
+                                                                         const float2* __restrict__ twt,
+                                                                         const Stencil st) {
+  __shared__ float2 lds[forward_lds<N, NF, true>()];
+  const int64_t U = ntiles * ((K + NF - 1) / NF);
+  const int64_t u0 = first_unit(U, gridDim.x, blockIdx.x);
+  const int64_t u1 = first_unit(U, gridDim.x, blockIdx.x + 1);
+  if (u0 >= u1) return;  // uniform over the workgroup
+  int par = 0;
+  forward_range<N, NF, POWER, REAL, STORE_NT_WHOLE, true>(s, Ns, F, y, K, D, H, twt, u0, u1, lds, par, &st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1133,6 +1212,9 @@ struct ols_plan_s {
   int segs = 0;   // segments per tile
   int nf = 1;     // filters per work unit of the forward kernel
   int flags = 0;  // OLS_POST_* and OLS_REAL
+  bool stencil_on = false;  // non-local stage (ols_plan_set_stencil)
+  int stencil_R = 0;        // its reach ahead (taps after the sample)
+  Stencil stencil{};
   void* bwd_mem = nullptr;  // the adjoint's scratch, allocated by ols_plan_reserve_backward
   BwdWorkspace bwd{};       // carved from bwd_mem for the adjoint's full grid
   float2* spectra = nullptr;
@@ -1204,17 +1286,44 @@ struct Kern {
     }
     return forward_fn_nf<1>(power, real);
   }
+  // The same for the kernel with the non-local stencil stage.
+  using StencilFn = void (*)(const void*, int64_t, const float2*, void*, int, int, int, int64_t, const float2*,
+                             const Stencil);
+  template <int NF>
+  static StencilFn stencil_fn_nf(bool power, bool real) {
+    if (real) {
+      constexpr int NFR = N <= BATCH_NF2_MAX_N ? NF : 1;
+      return power ? ols_forward_stencil_kernel<N, NFR, true, true> : ols_forward_stencil_kernel<N, NFR, false, true>;
+    }
+    return power ? ols_forward_stencil_kernel<N, NF, true, false> : ols_forward_stencil_kernel<N, NF, false, false>;
+  }
+  static StencilFn stencil_fn(int nf, int flags) {
+    const bool power = (flags & OLS_POST_POWER) != 0, real = (flags & OLS_REAL) != 0;
+    if constexpr (HAS_NF2) {
+      if (nf == 2) return stencil_fn_nf<2>(power, real);
+    }
+    return stencil_fn_nf<1>(power, real);
+  }
   static hipError_t forward(const ols_plan_s* p, const void* s, int64_t Ns, void* y, hipStream_t st) {
     const int64_t nseg = (Ns + p->H - 1) / p->H;
     const int64_t ntrans = (p->flags & OLS_REAL) ? (nseg + 1) / 2 : nseg;  // R2R: segment pairs
     const int64_t ntiles = (ntrans + GE::SEGS - 1) / GE::SEGS;
     const int64_t units = ntiles * ((p->K + p->nf - 1) / p->nf);
     const int64_t grid = units < p->grid ? units : p->grid;
-    hipLaunchKernelGGL(forward_fn(p->nf, p->flags), dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra, y,
-                       p->K, p->D, p->H, ntiles, p->twiddles);
+    if (p->stencil_on) {
+      // J <= 2 phases go out as one element per sample when y is aligned to it
+      Stencil sten = p->stencil;
+      const uintptr_t el = (uintptr_t)sten.J * (((p->flags & (OLS_REAL | OLS_POST_POWER)) != 0) ? 4 : 8);
+      sten.packed = sten.J <= 2 && (uintptr_t)y % el == 0;
+      hipLaunchKernelGGL(stencil_fn(p->nf, p->flags), dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra, y,
+                         p->K, p->D, p->H, ntiles, p->twiddles, sten);
+    } else
+      hipLaunchKernelGGL(forward_fn(p->nf, p->flags), dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra,
+                         y, p->K, p->D, p->H, ntiles, p->twiddles);
     return hipGetLastError();
   }
-  static hipError_t occupancy(int nf, int flags, int* blocks_per_cu) {
+  static hipError_t occupancy(int nf, int flags, bool stage, int* blocks_per_cu) {
+    if (stage) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, stencil_fn(nf, flags), GE::WG, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, forward_fn(nf, flags), GE::WG, 0);
   }
   // The adjoint: paired segments up to N = 2048 (ols_backward_pair_kernel),
@@ -1301,7 +1410,7 @@ struct RunForward {
 };
 template <int N>
 struct RunOccupancy {
-  static hipError_t run(int nf, int flags, int* b) { return Kern<N>::occupancy(nf, flags, b); }
+  static hipError_t run(int nf, int flags, bool stage, int* b) { return Kern<N>::occupancy(nf, flags, stage, b); }
 };
 template <int N>
 struct RunBwdOccupancy {
@@ -1440,7 +1549,8 @@ ols_status_t bwd_validate(ols_plan_t p, const void* s, int64_t Ns, const void* g
                           bool* done) {
   *done = false;
   if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
-  if (p->flags != OLS_POST_NONE) return fail(OLS_ERROR_UNSUPPORTED, "backward of a post-processed or R2R plan");
+  if (p->flags != OLS_POST_NONE || p->stencil_on)
+    return fail(OLS_ERROR_UNSUPPORTED, "backward of a post-processed or R2R plan");
   if (Ns < 0) return fail(OLS_ERROR_INVALID_VALUE, "N_s must be >= 0");
   if (!ds && !dh) {
     *done = true;
@@ -1558,7 +1668,7 @@ ols_status_t ols_plan_ex(ols_plan_t* plan, const void* h, int32_t K, int32_t M, 
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "hipDeviceGetAttribute"); }
     p->nf = (flags & OLS_REAL) ? choose_nf_real(N, K) : choose_nf(N, K);
     int per_cu = 0;
-    e = dispatch<RunOccupancy>(N, p->nf, flags, &per_cu);
+    e = dispatch<RunOccupancy>(N, p->nf, flags, false, &per_cu);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "occupancy query"); }
     if (per_cu < 1) per_cu = 1;
     p->grid = per_cu * p->cus;
@@ -1603,18 +1713,58 @@ ols_status_t ols_plan_update_filters(ols_plan_t p, const void* h, ols_stream_t s
 ols_status_t ols_plan_set_hop(ols_plan_t p, int32_t H) {
   if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
   const int Meff = (p->flags & OLS_POST_DERIVATIVE) ? p->M + 1 : p->M;
-  const int L = p->N - Meff + 1;
+  // a stencil needs sL unaliased outputs before each kept one and sR after it
+  const int sL = p->stencil_on ? p->stencil.L : 0, sR = p->stencil_on ? p->stencil_R : 0;
+  const int Hmax = p->N - (Meff - 1 + sL) - sR;
   if (H == 0) {
-    p->D = default_delay(p->N, Meff);
-    p->H = p->N - p->D;
+    p->D = stencil_delay(p->N, Meff, sL, sR);
+    p->H = stencil_hop(p->N, p->D, sR);
     return OLS_SUCCESS;
   }
-  if (H < 1 || H > L) return fail(OLS_ERROR_INVALID_VALUE, "hop must satisfy 1 <= H <= N-M+1");
-  int D = default_delay(p->N, Meff);
-  if (D + H > p->N) D = p->N - H;
+  if (H < 1 || H > Hmax) return fail(OLS_ERROR_INVALID_VALUE, "hop must satisfy 1 <= H <= N-M+1 (less the stencil's reach)");
+  int D = stencil_delay(p->N, Meff, sL, sR);
+  if (D + H + sR > p->N) D = p->N - H - sR;
   p->D = D;
   p->H = H;
   return OLS_SUCCESS;
+}
+
+ols_status_t ols_plan_set_stencil(ols_plan_t p, int32_t J, int32_t L, int32_t R, const float* w) {
+  try {
+    if (!p) return fail(OLS_ERROR_INVALID_VALUE, "plan is NULL");
+    const int Meff = (p->flags & OLS_POST_DERIVATIVE) ? p->M + 1 : p->M;
+    Stencil st{};
+    if (J != 0) {
+      if (J < 1 || J > STENCIL_MAX_PHASES) return fail(OLS_ERROR_INVALID_VALUE, "phases must be in [1, 4] (0 removes the stencil)");
+      if (L < 0 || R < 0 || L + 1 + R > STENCIL_MAX_TAPS)
+        return fail(OLS_ERROR_INVALID_VALUE, "the stencil needs left, right >= 0 and left + 1 + right <= 8 taps");
+      if (!w) return fail(OLS_ERROR_INVALID_VALUE, "weights are NULL");
+      if (Meff - 1 + L + R > p->N - 1)
+        return fail(OLS_ERROR_INVALID_VALUE, "M - 1 + left + right must be < N (no kept output would remain)");
+      st.J = J;
+      st.L = L;
+      st.T = L + 1 + R;
+      for (int j = 0; j < J; ++j)
+        for (int d = 0; d < st.T; ++d) st.w[j][d] = w[j * st.T + d];
+    }
+    // one filter per unit with the stage: with two, the stage kernels at
+    // N = 2048 spill registers and measured 5-15 % slower
+    const int nf = J != 0 ? 1 : ((p->flags & OLS_REAL) ? choose_nf_real(p->N, p->K) : choose_nf(p->N, p->K));
+    int per_cu = 0;
+    hipError_t e = dispatch<RunOccupancy>(p->N, nf, p->flags, J != 0, &per_cu);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    if (per_cu < 1) per_cu = 1;
+    p->nf = nf;
+    p->stencil_on = J != 0;
+    p->stencil = st;
+    p->stencil_R = J != 0 ? R : 0;
+    p->D = stencil_delay(p->N, Meff, p->stencil_on ? L : 0, p->stencil_R);
+    p->H = stencil_hop(p->N, p->D, p->stencil_R);
+    p->grid = per_cu * p->cus;
+    return OLS_SUCCESS;
+  } catch (...) {
+    return fail(OLS_ERROR_INTERNAL, "exception in ols_plan_set_stencil");
+  }
 }
 
 ols_status_t ols_plan_get_info(ols_plan_t p, int32_t* N, int32_t* H, int32_t* D, int32_t* K, int32_t* M) {
@@ -1653,7 +1803,7 @@ ols_status_t ols_plan_set_tiling(ols_plan_t p, int32_t nf, int32_t wpc) {
     if (nf == 0) nf = (p->flags & OLS_REAL) ? choose_nf_real(p->N, p->K) : choose_nf(p->N, p->K);
     if (!nf_allowed(p, nf)) return fail(OLS_ERROR_INVALID_VALUE, "filters_per_unit must be 1 or 2 (2 only for N <= 4096, R2R N <= 2048)");
     int per_cu = 0;
-    hipError_t e = dispatch<RunOccupancy>(p->N, nf, p->flags, &per_cu);
+    hipError_t e = dispatch<RunOccupancy>(p->N, nf, p->flags, p->stencil_on, &per_cu);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     if (per_cu < 1) per_cu = 1;
     if (wpc == 0) wpc = per_cu;
@@ -1672,7 +1822,7 @@ ols_status_t ols_plan_get_tiling(ols_plan_t p, int32_t* nf, int32_t* wpc, int32_
   if (wpc) *wpc = p->grid / p->cus;
   if (max_wpc) {
     int per_cu = 0;
-    hipError_t e = dispatch<RunOccupancy>(p->N, p->nf, p->flags, &per_cu);
+    hipError_t e = dispatch<RunOccupancy>(p->N, p->nf, p->flags, p->stencil_on, &per_cu);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     *max_wpc = per_cu < 1 ? 1 : per_cu;
   }
@@ -1704,8 +1854,9 @@ ols_status_t ols_forward(ols_plan_t p, const void* s, int64_t Ns, void* y, ols_s
     const size_t y_el = (real || (p->flags & OLS_POST_POWER)) ? 4 : 8;     // sample size of y
     if (((uintptr_t)s) % s_el || ((uintptr_t)y) % y_el)
       return fail(OLS_ERROR_INVALID_VALUE, "s or y is not aligned to its element type");
-    if (Ns > ((int64_t)1 << 56) / 8 / p->K) return fail(OLS_ERROR_INVALID_VALUE, "K*N_s*8 overflows");
-    if (ranges_overlap(s, (size_t)Ns * s_el, y, (size_t)Ns * (size_t)p->K * y_el))
+    const int J = p->stencil_on ? p->stencil.J : 1;  // outputs per sample
+    if (Ns > ((int64_t)1 << 56) / 8 / p->K / J) return fail(OLS_ERROR_INVALID_VALUE, "K*J*N_s*8 overflows");
+    if (ranges_overlap(s, (size_t)Ns * s_el, y, (size_t)Ns * (size_t)p->K * (size_t)J * y_el))
       return fail(OLS_ERROR_INVALID_VALUE, "y overlaps s (out of place only)");
     hipError_t e = dispatch<RunForward>(p->N, (const ols_plan_s*)p, s, Ns, y, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward launch");

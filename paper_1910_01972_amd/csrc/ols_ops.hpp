@@ -3,6 +3,8 @@
 // the device kernels and by the host emulator used in CPU tests.
 #pragma once
 
+#include <type_traits>
+
 #include "ols_fft.hpp"
 
 namespace ols {
@@ -161,6 +163,29 @@ OLS_HD void out_store(P p, float2 v) {
   out_store<MODE>(&p->y, v.y);
 }
 
+// Vector elements (packed stencil phases): one store of the whole vector.
+template <int MODE, typename P>
+OLS_HD void out_store(P p, f32x2 v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (MODE != STORE_PLAIN) {
+    __builtin_nontemporal_store(v, p);
+    return;
+  }
+#endif
+  *p = v;
+}
+
+template <int MODE, typename P>
+OLS_HD void out_store(P p, f32x4 v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (MODE != STORE_PLAIN) {
+    __builtin_nontemporal_store(v, p);
+    return;
+  }
+#endif
+  *p = v;
+}
+
 #if defined(__HIP_DEVICE_COMPILE__)
 constexpr int CPOL_NT = 2;  // cache-policy operand of the buffer builtins: nt
 
@@ -183,6 +208,22 @@ __device__ __forceinline__ void buffer_store(float2 v, __amdgpu_buffer_rsrc_t rs
 template <int CPOL>
 __device__ __forceinline__ void buffer_store(float v, __amdgpu_buffer_rsrc_t rs, int off) {
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, 0, CPOL);
+}
+
+template <int CPOL>
+__device__ __forceinline__ void buffer_store(f32x2 v, __amdgpu_buffer_rsrc_t rs, int off) {
+  buffer_store<CPOL>(make_float2(v.x, v.y), rs, off);
+}
+
+template <int CPOL>
+__device__ __forceinline__ void buffer_store(f32x4 v, __amdgpu_buffer_rsrc_t rs, int off) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 d;
+  d.x = __float_as_uint(v.x);
+  d.y = __float_as_uint(v.y);
+  d.z = __float_as_uint(v.z);
+  d.w = __float_as_uint(v.w);
+  __builtin_amdgcn_raw_buffer_store_b128(d, rs, off, 0, CPOL);
 }
 #endif
 
@@ -218,7 +259,8 @@ OLS_HD int granule_phase(const T* p) {
 // boundaries (D a multiple of C, and D + H = N as with the default hop),
 // otherwise its head and tail granules may go non-temporal, two granules in
 // H / LS.  The choice of policy never changes what is written.
-template <int N, int MODE, typename T, typename V>
+// Registers R0 .. R0 + NR - 1 only (callers that produce the values in parts).
+template <int N, int MODE, int R0 = 0, int NR = 16, typename T, typename V>
 OLS_HD void store_segment(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H, int g, V val) {
   // T is float2 or float, with the pointer's address space (gptr) if any
   constexpr int LS = 64 / (int)sizeof(T);                // outputs per 64-byte granule
@@ -237,11 +279,11 @@ OLS_HD void store_segment(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D,
         out_rsrc(wave_uniform_ptr(yrow + out0), __builtin_amdgcn_readfirstlane(cnt * (int)sizeof(T)));
     if (whole) {
 #pragma unroll
-      for (int reg = 0; reg < 16; ++reg)
+      for (int reg = R0; reg < R0 + NR; ++reg)
         buffer_store<CPOL_NT>(val(reg), rs, (g + time_pos_const<N>(reg) - D) * (int)sizeof(T));
     } else {
 #pragma unroll
-      for (int reg = 0; reg < 16; ++reg)
+      for (int reg = R0; reg < R0 + NR; ++reg)
         buffer_store<0>(val(reg), rs, (g + time_pos_const<N>(reg) - D) * (int)sizeof(T));
     }
     return;
@@ -250,13 +292,13 @@ OLS_HD void store_segment(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D,
   T* base = yrow + (out0 - D);
   if (MODE == STORE_NT || (MODE == STORE_NT_WHOLE && whole)) {
 #pragma unroll
-    for (int reg = 0; reg < 16; ++reg) {
+    for (int reg = R0; reg < R0 + NR; ++reg) {
       const int p = g + time_pos_const<N>(reg);
       if (p >= D && p < D + cnt) out_store<STORE_NT>(base + p, val(reg));
     }
   } else {
 #pragma unroll
-    for (int reg = 0; reg < 16; ++reg) {
+    for (int reg = R0; reg < R0 + NR; ++reg) {
       const int p = g + time_pos_const<N>(reg);
       if (p >= D && p < D + cnt) out_store<STORE_PLAIN>(base + p, val(reg));
     }
@@ -288,6 +330,220 @@ OLS_HD void store_valid(const float2 (&x)[16], P yrow, int64_t Ns, int64_t out0,
 template <int N, int MODE = STORE_PLAIN, class P>
 OLS_HD void store_valid_power(const float2 (&x)[16], P yrow, int64_t Ns, int64_t out0, int D, int H, int g) {
   store_kept<N, MODE>(x, yrow, Ns, out0, D, H, g, Power());
+}
+
+// ---------------------------------------------------------------------------
+// Non-local post-processing (sec. 4: an output may depend on its neighbours,
+// the paper's examples being the numerical derivative and interpolation).
+// After the inverse transform the segment's outputs are written to LDS in
+// natural order; each kept position p then combines the outputs at p - L ..
+// p + R into J values by a stencil with real weights and J outputs (phases) per sample,
+//     z[J n + j] = sum_{d=-L}^{R} w[j][d + L] * y[n + d],   n = out0 + p - D,
+// optionally followed by the power.  The kept positions must see unaliased
+// neighbours: D >= M - 1 + L and D + H + R <= N (stencil_delay), so the last
+// segment also reads samples past N_s, which the zero-filled segment load
+// makes eq. (1)'s tail.  Any hop up to N - D - R gives the same result.
+// ---------------------------------------------------------------------------
+constexpr int STENCIL_MAX_PHASES = 4;  // J: outputs per sample
+constexpr int STENCIL_MAX_TAPS = 8;    // T = L + 1 + R
+constexpr int STENCIL_PAD = 8;         // staged slots before and after a segment (>= max L, R)
+
+struct Stencil {
+  int J;       // phases, 1 .. STENCIL_MAX_PHASES
+  int L;       // taps before the sample
+  int T;       // taps, L + 1 + R
+  int packed;  // the output is aligned to J elements: J <= 2 takes stage_store_packed
+  float w[STENCIL_MAX_PHASES][STENCIL_MAX_TAPS];  // w[j][d + L]; zero past T and J
+};
+
+// LDS slots of one staged segment: position p at STENCIL_PAD + p, so every
+// tap of every position of the transform stays inside its own segment slots.
+template <int N>
+constexpr int stage_stride() { return N + 2 * STENCIL_PAD; }
+
+// First kept position of a plan whose stencil reaches L back and R ahead
+// (Meff: taps of the filter as applied): the default_delay rounding when
+// D + R <= N - 1 still holds, else exactly Meff - 1 + L.  The hop may reach
+// N - D - R.
+OLS_HD int stencil_delay(int N, int Meff, int L, int R) {
+  const int lo = Meff - 1 + L;
+  const int d = (lo + 15) / 16 * 16;
+  return d + R <= N - 1 ? d : lo;
+}
+
+// Default hop with a stencil: N - D - R, rounded down to a multiple of 16
+// samples when it is at least 16, so that segments keep starting on the
+// 128-byte output grid (as the plain default hop does).
+OLS_HD int stencil_hop(int N, int D, int R) {
+  const int h = N - D - R;
+  return h >= 16 ? h & ~15 : h;
+}
+
+// The transform output of lane g (register reg = circular position
+// g + time_pos_const(reg)) into the segment's LDS slots.
+template <int N>
+OLS_HD void stage_write(float2* __restrict__ region, const float2 (&x)[16], int g) {
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) region[STENCIL_PAD + g + time_pos_const<N>(reg)] = x[reg];
+}
+
+// Phase j of the stencil at the 16 positions of lane g.  The tap loop runs T
+// times (wave-uniform); position p + d - L is read for tap d, inside the
+// segment's slots for every p (|d - L| <= STENCIL_PAD), from staged outputs
+// for every kept p.
+template <int N, class S>
+OLS_HD void stage_phase(float2 (&acc)[16], const float2* __restrict__ region, const S& st, int j, int g) {
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) acc[reg] = make_float2(0.f, 0.f);
+  const float2* src = region + STENCIL_PAD + g - st.L;
+  for (int d = 0; d < st.T; ++d) {
+    const float wd = st.w[j][d];
+#pragma unroll
+    for (int reg = 0; reg < 16; ++reg) {
+      const float2 v = src[d + time_pos_const<N>(reg)];
+      acc[reg].x = fmaf(wd, v.x, acc[reg].x);
+      acc[reg].y = fmaf(wd, v.y, acc[reg].y);
+    }
+  }
+}
+
+// Store of phase j of a segment's kept positions: position p (D <= p <
+// D + cnt) goes to element J * (out0 + p - D) + j of the row.  Rows with
+// J > 1 are written J elements apart by each instruction, so the default
+// cache policy lets the phases of a granule merge in L2.  A wave-wide
+// transform (G >= 64) stores through a buffer resource over exactly the
+// segment's J * cnt elements, whose range check drops the other positions.
+template <int N, typename T, typename V>
+OLS_HD void store_phase(T* __restrict__ yrow, int64_t Ns, int64_t out0, int D, int H, int g, int J, int j, V val) {
+  const int cnt = kept_count(Ns, out0, H);
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (Geo<N>::G >= 64) {
+    const __amdgpu_buffer_rsrc_t rs = out_rsrc(wave_uniform_ptr(yrow + (int64_t)J * out0),
+                                               __builtin_amdgcn_readfirstlane(J * cnt * (int)sizeof(T)));
+#pragma unroll
+    for (int reg = 0; reg < 16; ++reg)
+      buffer_store<0>(val(reg), rs, ((g + time_pos_const<N>(reg) - D) * J + j) * (int)sizeof(T));
+    return;
+  }
+#endif
+  T* base = yrow + (int64_t)J * out0;
+#pragma unroll
+  for (int reg = 0; reg < 16; ++reg) {
+    const int p = g + time_pos_const<N>(reg);
+    if (p >= D && p < D + cnt) out_store<STORE_PLAIN>(base + (p - D) * J + j, val(reg));
+  }
+}
+
+// All JC phases at positions R0 .. R0 + NR - 1 of lane g (acc[j][reg - R0]),
+// each tap read from LDS once.
+template <int N, int JC, int R0, int NR, class S>
+OLS_HD void stage_phases(float2 (&acc)[JC][NR], const float2* __restrict__ region, const S& st, int g) {
+#pragma unroll
+  for (int j = 0; j < JC; ++j)
+#pragma unroll
+    for (int i = 0; i < NR; ++i) acc[j][i] = make_float2(0.f, 0.f);
+  const float2* src = region + STENCIL_PAD + g - st.L;
+  for (int d = 0; d < st.T; ++d) {
+    float wd[JC];
+#pragma unroll
+    for (int j = 0; j < JC; ++j) wd[j] = st.w[j][d];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const float2 v = src[d + time_pos_const<N>(R0 + i)];
+#pragma unroll
+      for (int j = 0; j < JC; ++j) {
+        acc[j][i].x = fmaf(wd[j], v.x, acc[j][i].x);
+        acc[j][i].y = fmaf(wd[j], v.y, acc[j][i].y);
+      }
+    }
+  }
+}
+
+// One (JC = 1) or two phases per position written as one element: a float2,
+// float or the vector of the two phases, so that each store instruction
+// covers consecutive positions whole and the store policy of store_segment
+// (non-temporal for whole 64-byte granules) applies as to a plain row.
+// yrow must be aligned to the element (Stencil::packed).
+// The positions go in parts of STAGE_PART registers, which bounds the live
+// accumulators.
+constexpr int STAGE_PART = 4;
+template <int N, int JC, bool POWER, bool REAL, int SMODE, int R0, class S, class P>
+OLS_HD void stage_store_packed_part(const float2* __restrict__ region, const S& st, P yrow, int64_t Ns, int64_t out0,
+                                    int D, int H, int g) {
+  constexpr int NR = STAGE_PART;
+  float2 acc[JC][NR];
+  stage_phases<N, JC, R0, NR>(acc, region, st, g);
+  if constexpr (REAL || POWER) {
+    // float rows: component c of each phase (REAL) or the power (POWER)
+    auto val = [&](int reg, int c) {
+      float v[JC];
+#pragma unroll
+      for (int j = 0; j < JC; ++j) {
+        const float2 a = acc[j][reg - R0];
+        v[j] = REAL ? (c == 0 ? (POWER ? a.x * a.x : a.x) : (POWER ? a.y * a.y : a.y)) : Power()(a);
+      }
+      if constexpr (JC == 1) return v[0];
+      else return f32x2{v[0], v[1]};
+    };
+    using V = typename std::conditional<JC == 1, float, f32x2>::type;
+    const auto yv = rebind_ptr<V>(yrow);
+    store_segment<N, SMODE, R0, NR>(yv, Ns, out0, D, H, g, [&](int reg) { return val(reg, 0); });
+    if constexpr (REAL)
+      store_segment<N, SMODE, R0, NR>(yv, Ns, out0 + H, D, H, g, [&](int reg) { return val(reg, 1); });
+  } else if constexpr (JC == 1) {
+    store_segment<N, SMODE, R0, NR>(yrow, Ns, out0, D, H, g, [&](int reg) { return acc[0][reg - R0]; });
+  } else {
+    const auto yv = rebind_ptr<f32x4>(yrow);
+    store_segment<N, SMODE, R0, NR>(yv, Ns, out0, D, H, g, [&](int reg) {
+      const float2 a = acc[0][reg - R0], b = acc[1][reg - R0];
+      return f32x4{a.x, a.y, b.x, b.y};
+    });
+  }
+}
+
+template <int N, int JC, bool POWER, bool REAL, int SMODE, class S, class P>
+OLS_HD void stage_store_packed(const float2* __restrict__ region, const S& st, P yrow, int64_t Ns, int64_t out0,
+                               int D, int H, int g) {
+  static_assert(JC == 1 || JC == 2, "one or two phases per element");
+  stage_store_packed_part<N, JC, POWER, REAL, SMODE, 0>(region, st, yrow, Ns, out0, D, H, g);
+  stage_store_packed_part<N, JC, POWER, REAL, SMODE, STAGE_PART>(region, st, yrow, Ns, out0, D, H, g);
+  if constexpr (STAGE_PART < 8) {
+    stage_store_packed_part<N, JC, POWER, REAL, SMODE, 2 * STAGE_PART>(region, st, yrow, Ns, out0, D, H, g);
+    stage_store_packed_part<N, JC, POWER, REAL, SMODE, 3 * STAGE_PART>(region, st, yrow, Ns, out0, D, H, g);
+  }
+}
+
+// Every phase of the stencil for one filter's staged segment, stored to row
+// yrow (J * N_s elements; float for POWER or REAL).  REAL: the staged values
+// hold segment 2q in the real part and 2q + 1 in the imaginary part (R2R
+// pairs), stored from out0 and out0 + H.  J <= 2 with an aligned output takes
+// the packed form; otherwise each phase is computed and stored on its own,
+// J elements apart.
+template <int N, bool POWER, bool REAL, int SMODE = STORE_PLAIN, class S, class P>
+OLS_HD void stage_store(const float2* __restrict__ region, const S& st, P yrow, int64_t Ns, int64_t out0, int D,
+                        int H, int g) {
+  if (st.packed && st.J == 1) {
+    stage_store_packed<N, 1, POWER, REAL, SMODE>(region, st, yrow, Ns, out0, D, H, g);
+    return;
+  }
+  if (st.packed && st.J == 2) {
+    stage_store_packed<N, 2, POWER, REAL, SMODE>(region, st, yrow, Ns, out0, D, H, g);
+    return;
+  }
+  for (int j = 0; j < st.J; ++j) {
+    float2 acc[16];
+    stage_phase<N>(acc, region, st, j, g);
+    if constexpr (REAL) {
+      store_phase<N>(yrow, Ns, out0, D, H, g, st.J, j,
+                     [&](int reg) { return POWER ? acc[reg].x * acc[reg].x : acc[reg].x; });
+      store_phase<N>(yrow, Ns, out0 + H, D, H, g, st.J, j,
+                     [&](int reg) { return POWER ? acc[reg].y * acc[reg].y : acc[reg].y; });
+    } else if constexpr (POWER) {
+      store_phase<N>(yrow, Ns, out0, D, H, g, st.J, j, [&](int reg) { return Power()(acc[reg]); });
+    } else {
+      store_phase<N>(yrow, Ns, out0, D, H, g, st.J, j, [&](int reg) { return acc[reg]; });
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -31,6 +31,12 @@ def emu() -> ctypes.CDLL:
         L.ols_emu_wave_local.restype = I32
         L.ols_emu_backward.argtypes = [I32, P, I64, P, P, I32, I32, I32, I32, I32, P, P]
         L.ols_emu_backward.restype = I32
+        L.ols_emu_forward_stencil.argtypes = [I32, P, I64, P, I32, I32, I32, I32, I32, I32, I32, I32, I32, P, I32, P]
+        L.ols_emu_forward_stencil.restype = I32
+        L.ols_emu_stencil_delay.argtypes = [I32, I32, I32, I32]
+        L.ols_emu_stencil_delay.restype = I32
+        L.ols_emu_stencil_hop.argtypes = [I32, I32, I32]
+        L.ols_emu_stencil_hop.restype = I32
         L.ols_emu_cost_model.argtypes = [I32, I32, I32]
         L.ols_emu_cost_model.restype = I32
         for f in (L.ols_emu_forward, L.ols_emu_spectra, L.ols_emu_lds_report, L.ols_emu_geometry):
@@ -120,6 +126,43 @@ def forward_post(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int
         raise RuntimeError(f"emulator returned {rc}")
     ok = bool(np.all(np.isnan(ybuf[:guard])) and np.all(np.isnan(ybuf[guard + K * Ns:])))
     return ybuf[guard:guard + K * Ns].reshape(K, Ns).copy(), ok
+
+
+def stencil_delay(N: int, Meff: int, left: int, right: int) -> int:
+    """First kept position of a plan with a stencil (hop at most N - D - right)."""
+    return int(emu().ols_emu_stencil_delay(N, Meff, left, right))
+
+
+def stencil_hop(N: int, D: int, right: int) -> int:
+    """Default hop of a plan with a stencil."""
+    return int(emu().ols_emu_stencil_hop(N, D, right))
+
+
+def forward_stencil(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, post: int, weights, left: int,
+                    guard: int = 4096, packed: bool = True):
+    """forward_post followed by the non-local stencil stage: rows of J * N_s
+    outputs inside NaN guard bands (packed=False: the per-phase store form
+    for every J).  Returns (y, y_guard_ok)."""
+    w = np.ascontiguousarray(np.atleast_2d(np.asarray(weights, dtype=np.float32)))
+    J, T = w.shape
+    real = bool(post & 4)
+    cdt = np.float32 if real else np.complex64
+    h = np.ascontiguousarray(h, dtype=cdt)
+    s = np.ascontiguousarray(s, dtype=cdt)
+    K, M = h.shape
+    Ns = int(s.shape[0])
+    dt, esz = (np.float32, 4) if post & 6 else (np.complex64, 8)
+    sbuf = np.full(Ns + 2 * guard, np.nan, dtype=cdt)
+    sbuf[guard:guard + Ns] = s
+    n_out = K * J * Ns
+    ybuf = np.full(n_out + 2 * guard, np.nan, dtype=dt)
+    rc = emu().ols_emu_forward_stencil(N, ctypes.c_void_p(sbuf.ctypes.data + guard * sbuf.itemsize), Ns, _ptr(h), K,
+                                       M, D, H, grid, int(post), J, int(left), T - 1 - int(left), _ptr(w),
+                                       int(bool(packed)), ctypes.c_void_p(ybuf.ctypes.data + guard * esz))
+    if rc != 0:
+        raise RuntimeError(f"emulator returned {rc}")
+    ok = bool(np.all(np.isnan(ybuf[:guard])) and np.all(np.isnan(ybuf[guard + n_out:])))
+    return ybuf[guard:guard + n_out].reshape(K, J * Ns).copy(), ok
 
 
 def backward(s: np.ndarray, gy: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, guard: int = 4096):

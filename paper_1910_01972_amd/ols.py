@@ -33,6 +33,13 @@ def _check_c64(t: torch.Tensor, name: str, ndim: int, dtype=torch.complex64) -> 
         raise ValueError(f"{name} must be contiguous")
 
 
+# Stencils of the non-local stage, as (weights[J][T], left): the backward
+# difference, and the cubic (four-point Lagrange) midpoint interpolation that
+# writes each sample followed by the value half a sample later.
+DIFFERENCE_STENCIL = ([[-1.0, 1.0]], 1)
+MIDPOINT_CUBIC_STENCIL = ([[0.0, 1.0, 0.0, 0.0], [-1.0 / 16, 9.0 / 16, 9.0 / 16, -1.0 / 16]], 1)
+
+
 class OLSPlan:
     """Filter bank h[K][M] (complex64, on the GPU) prepared for FFT length N.
 
@@ -41,9 +48,12 @@ class OLSPlan:
     backward first difference of each output row (folded into the spectra)
     and the per-element power |y|^2 (float32 output).  A float32 filter bank
     makes a real-to-real (R2R) plan: the signal and the output are float32.
+    stencil = (weights[J][T], left) adds the non-local stage of sec. 4 (see
+    set_stencil).
     """
 
-    def __init__(self, h: torch.Tensor, N: int = 0, stream=None, derivative: bool = False, power: bool = False):
+    def __init__(self, h: torch.Tensor, N: int = 0, stream=None, derivative: bool = False, power: bool = False,
+                 stencil=None):
         self.real = isinstance(h, torch.Tensor) and h.dtype == torch.float32
         self._in_dtype = torch.float32 if self.real else torch.complex64
         _check_c64(h, "h", 2, self._in_dtype)
@@ -57,6 +67,28 @@ class OLSPlan:
             check(lib().ols_plan_ex(ctypes.byref(self._handle), ctypes.c_void_p(h.data_ptr()), self.K, self.M, int(N),
                                     self.flags, _stream_handle(stream)), "ols_plan_ex")
         self._remember_filters(h)
+        self.phases = 1
+        if stencil is not None:
+            self.set_stencil(*stencil)
+
+    def set_stencil(self, weights, left: int = 0) -> None:
+        """Non-local post-processing inside the forward kernel (sec. 4): every
+        output sample n yields J values z[J n + j] = sum_d w[j][d + left] *
+        y[n + d], d = -left .. T-1-left, from the segment's outputs staged on
+        chip (zero history before 0, the convolution's tail past N_s).
+        forward() then returns rows of J * N_s samples.  weights=None removes
+        the stencil.  Resets the hop and the workgroups per CU."""
+        if weights is None:
+            check(lib().ols_plan_set_stencil(self.handle, 0, 0, 0, None), "ols_plan_set_stencil")
+            self.phases = 1
+            return
+        rows = [[float(v) for v in row] for row in weights]
+        J, T = len(rows), len(rows[0]) if rows else 0
+        if J == 0 or T == 0 or any(len(r) != T for r in rows):
+            raise ValueError("weights must be a non-empty J x T table")
+        buf = (ctypes.c_float * (J * T))(*[v for r in rows for v in r])
+        check(lib().ols_plan_set_stencil(self.handle, J, int(left), T - 1 - int(left), buf), "ols_plan_set_stencil")
+        self.phases = J
 
     def _remember_filters(self, h: torch.Tensor) -> None:
         # a reference keeps the memory from being reused by another tensor, so
@@ -139,17 +171,19 @@ class OLSPlan:
 
     def forward(self, s: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """y[K][N_s] = eq. (1) of s with every filter (zero history),
-        post-processed as the plan's flags say."""
+        post-processed as the plan's flags and stencil say ([K][J N_s] with a
+        stencil of J phases)."""
         _check_c64(s, "s", 1, self._in_dtype)
         Ns = int(s.shape[0])
         out_dtype = self._out_dtype
+        cols = self.phases * Ns  # J outputs per sample with a stencil
         if y is None:
-            y = torch.empty((self.K, Ns), dtype=out_dtype, device=s.device)
+            y = torch.empty((self.K, cols), dtype=out_dtype, device=s.device)
         else:
             if y.dtype != out_dtype or y.device.type != "cuda" or not y.is_contiguous():
                 raise ValueError(f"y must be a contiguous {out_dtype} GPU tensor")
-            if tuple(y.shape) != (self.K, Ns):
-                raise ValueError("y must have shape (K, N_s)")
+            if tuple(y.shape) != (self.K, cols):
+                raise ValueError("y must have shape (K, J * N_s)")
         check(lib().ols_forward(self.handle, ctypes.c_void_p(s.data_ptr()), Ns, ctypes.c_void_p(y.data_ptr()),
                                 _stream_handle(stream)), "ols_forward")
         return y
@@ -371,10 +405,10 @@ class OLSBatched:
 
 
 def ols_conv(s: torch.Tensor, h: torch.Tensor, N: int = 0, stream=None, derivative: bool = False,
-             power: bool = False) -> torch.Tensor:
+             power: bool = False, stencil=None) -> torch.Tensor:
     """One-shot overlap-and-save convolution: y[K][N_s] (post-processed as
-    OLSPlan's flags select)."""
-    plan = OLSPlan(h, N=N, stream=stream, derivative=derivative, power=power)
+    OLSPlan's flags and stencil select)."""
+    plan = OLSPlan(h, N=N, stream=stream, derivative=derivative, power=power, stencil=stencil)
     try:
         return plan.forward(s, stream=stream)
     finally:

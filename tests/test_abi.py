@@ -143,3 +143,17 @@ def test_batched_workspace_grows_with_items():
 
     s1, s2 = size(1), size(2)
     assert s2 - s1 >= 256 * 8 and s1 % 256 == 0
+
+
+def test_binding_imports_and_named_stencils():
+    """The Python binding imports without a GPU, and its named stencils are the
+    backward difference and the four-point Lagrange midpoint interpolation."""
+    import numpy as np
+    from oracle import post
+    from paper_1910_01972_amd import ols
+
+    w, left = ols.DIFFERENCE_STENCIL
+    assert left == 1 and np.allclose(w, [[-1.0, 1.0]])
+    w, left = ols.MIDPOINT_CUBIC_STENCIL
+    ow, oleft = post.midpoint_interpolation_stencil(1, 2)
+    assert left == oleft and np.allclose(w, ow, rtol=0, atol=1e-15)

@@ -292,3 +292,103 @@ def test_cost_model_choice():
                 if len(order) > 1 and abs(costs[order[0]] - costs[order[1]]) < 1e-12 * costs[order[0]]:
                     continue
                 assert got == order[0], (K, M, max_n, got, costs)
+
+
+# ----------------------------------------------------------- non-local stage
+
+_RNG_W = np.random.default_rng(2024)
+STENCILS = {
+    "difference": (np.array([[-1.0, 1.0]]), 1),
+    "central": (np.array([[-0.5, 0.0, 0.5]]), 1),
+    "midpoint_cubic": post.midpoint_interpolation_stencil(1, 2),
+    "wide3": (_RNG_W.uniform(-1, 1, (3, 6)), 2),        # J = 3, taps -2 .. 3
+    "ahead4": (_RNG_W.uniform(-1, 1, (4, 8)), 0),       # J = 4, taps 0 .. 7
+    "behind": (_RNG_W.uniform(-1, 1, (2, 8)), 7),       # taps -7 .. 0
+}
+
+STENCIL_CASES = [
+    # (Ns, K, M, N, flags, stencil)
+    (1, 1, 1, 256, 0, "midpoint_cubic"),
+    (200, 2, 3, 256, 0, "ahead4"),            # fewer samples than one segment
+    (3001, 3, 40, 256, 0, "wide3"),
+    (3001, 3, 40, 256, 2, "midpoint_cubic"),  # power of the interpolated value
+    (5000, 2, 64, 512, 1, "central"),         # stencil of the derivative
+    (9000, 4, 100, 1024, 0, "behind"),
+    (9000, 3, 100, 1024, 4, "midpoint_cubic"),  # R2R
+    (20000, 3, 513, 2048, 0, "midpoint_cubic"),
+    (20000, 4, 256, 2048, 2, "difference"),
+    (20000, 3, 300, 2048, 4 | 2, "wide3"),
+    (30000, 3, 1000, 4096, 0, "ahead4"),
+    (40000, 2, 700, 8192, 1 | 2, "midpoint_cubic"),
+    (40000, 2, 8185, 8192, 0, "difference"),   # M - 1 + left + right = N - 1: hop 1
+]
+
+
+def _stencil_ref(s, h, flags, w, left):
+    real = bool(flags & 4)
+    hh = h
+    if flags & 1:  # derivative first: the filter followed by [1, -1]
+        hh = np.concatenate([h, np.zeros((h.shape[0], 1), h.dtype)], axis=1)
+        hh[:, 1:] -= h
+    ref = post.conv_stencil_real(s, hh, w, left) if real else post.conv_stencil(s, hh, w, left)
+    if flags & 2:
+        ref = ref * ref if real else post.power(ref)
+    return ref
+
+
+@pytest.mark.parametrize("Ns,K,M,N,flags,name", STENCIL_CASES)
+def test_stencil_stage_vs_oracle(Ns, K, M, N, flags, name):
+    """The non-local stage (sec. 4) through the kernel dataflow: outputs staged
+    per segment, J phases per kept position, against the oracle's stencil of
+    eq. (1) (and its tail past N_s)."""
+    w, left = STENCILS[name]
+    right = w.shape[1] - 1 - left
+    real = bool(flags & 4)
+    if real:
+        s, h = workloads.make_real_signal_filters(Ns, K, M, seed=Ns + M)
+    else:
+        s, h = workloads.make_signal_filters(Ns, K, M, seed=Ns + M)
+    Meff = M + 1 if flags & 1 else M
+    D = emu.stencil_delay(N, Meff, left, right)
+    H = emu.stencil_hop(N, D, right)
+    assert D >= Meff - 1 + left and 1 <= H <= N - D - right
+    ref = _stencil_ref(s, h, flags, w, left)
+    for packed in (True, False):  # the packed form (J <= 2) and the per-phase one
+        y, ok = emu.forward_stencil(s, h, N, D, H, grid=7, post=flags, weights=w, left=left, packed=packed)
+        assert ok and not np.isnan(y).any()
+        assert y.shape == ref.shape == (K, w.shape[0] * Ns)
+        assert np.all(_rel(y, ref) <= 1e-5), (packed, _rel(y, ref))
+
+
+@pytest.mark.parametrize("N,H", [(256, 1), (256, 100), (1024, 700), (2048, 1500)])
+def test_stencil_stage_hop_invariance(N, H):
+    """Any hop the stencil's reach allows gives the same output (sec. 3.2)."""
+    w, left = STENCILS["wide3"]
+    right = w.shape[1] - 1 - left
+    s, h = workloads.make_signal_filters(6000, 2, 90, seed=91)
+    D = emu.stencil_delay(N, 90, left, right)
+    if D + H + right > N:
+        D = N - H - right
+    assert D >= 89 + left
+    y, ok = emu.forward_stencil(s, h, N, D, H, grid=5, post=0, weights=w, left=left)
+    assert ok and np.all(_rel(y, _stencil_ref(s, h, 0, w, left)) <= 1e-5)
+
+
+def test_stencil_delay_rule():
+    for N in (256, 1024, 8192):
+        for Meff in (1, 2, 17, 100, N - 14, N - 8):
+            for L in range(0, 8):
+                for R in range(0, 8 - L):
+                    if Meff - 1 + L + R > N - 1:
+                        continue
+                    D = emu.stencil_delay(N, Meff, L, R)
+                    assert D >= Meff - 1 + L and D + R <= N - 1
+                    if D != Meff - 1 + L:  # rounded up to 16 samples only when it still fits
+                        assert D % 16 == 0 and D - (Meff - 1 + L) < 16
+                    else:
+                        assert D % 16 == 0 or ((Meff - 1 + L + 15) // 16 * 16) + R > N - 1
+    assert emu.stencil_delay(2048, 256, 0, 0) == default_delay(2048, 256)
+    # default hop: a multiple of 16 when at least 16, never past N - D - R
+    for N, D, R in ((2048, 256, 2), (2048, 256, 0), (256, 250, 3), (256, 240, 1), (8192, 8184, 7)):
+        H = emu.stencil_hop(N, D, R)
+        assert 1 <= H <= N - D - R and (H % 16 == 0 or H < 16) and N - D - R - H < 16
