@@ -157,12 +157,11 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
   using GE = Geo<N>;
   const int KG = (K + NF - 1) / NF;
   std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
-  int64_t tile = u0 / KG;
-  int rg = (int)(u0 - tile * KG);
+  UnitWalk w(u0, KG);  // the device kernels' walk
   auto forward_tile = [&]() {
     for (int t = 0; t < GE::WG; ++t) {
       const int grp = t / GE::G, g = t % GE::G;
-      const int64_t seg = tile * GE::SEGS + grp;
+      const int64_t seg = w.tile * GE::SEGS + grp;
       float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
       if (real) load_segment_pair<N>(x, reinterpret_cast<const float*>(s), Ns, seg * 2 * H - D, H, g);
       else load_segment<N>(x, s, Ns, seg * H - D, g);
@@ -172,13 +171,12 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
   };
   forward_tile();
   for (int64_t u = u0; u < u1; ++u) {
-    if (rg == KG) {
-      rg = 0;
-      ++tile;
+    if (w.tile_done(KG)) {
+      w.next_tile();
       forward_tile();
     }
     for (int f = 0; f < NF; ++f) {
-      const int r = rg * NF + f;
+      const int r = w.rg * NF + f;
       if (r >= K) continue;  // padded last group: computed on the device, never stored
       for (int t = 0; t < GE::WG; ++t) {
         const int g = t % GE::G;
@@ -197,7 +195,7 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
           std::vector<float2> region(stage_stride<N>(), make_float2(NAN, NAN));
           for (int g = 0; g < GE::G; ++g)
             stage_write<N>(region.data(), *reinterpret_cast<const float2(*)[16]>(xs[grp * GE::G + g].data()), g);
-          const int64_t seg = tile * GE::SEGS + grp;
+          const int64_t seg = w.tile * GE::SEGS + grp;
           float* yr = reinterpret_cast<float*>(y) + row;
           for (int g = 0; g < GE::G; ++g) {
             if (real && power) stage_store<N, true, true>(region.data(), *st, yr, Ns, seg * 2 * H, D, H, g);
@@ -210,7 +208,7 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
       }
       for (int t = 0; t < GE::WG; ++t) {
         const int grp = t / GE::G, g = t % GE::G;
-        const int64_t seg = tile * GE::SEGS + grp;
+        const int64_t seg = w.tile * GE::SEGS + grp;
         const float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
         float* yr = reinterpret_cast<float*>(y) + (int64_t)r * Ns;
         if (real && power) store_valid_pair<N, true>(x, yr, Ns, seg * 2 * H, D, H, g);
@@ -219,7 +217,7 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
         else store_valid<N>(x, y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
       }
     }
-    ++rg;
+    w.leave();
   }
 }
 

@@ -227,8 +227,7 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
   const int KG = (K + NF - 1) / NF;  // filter groups
   const int64_t step = REAL ? 2 * (int64_t)H : H;  // signal advance per transform
 
-  int64_t tile = u0 / KG;
-  int rg = (int)(u0 - tile * KG);
+  UnitWalk w(u0, KG);
   float2 A[16], xa[NF][16], xb[NF][16];
   // all data lives in global memory: the batched kernel reads these pointers
   // from its item table, where the compiler cannot infer that by itself
@@ -324,23 +323,22 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
     }
   };
 
-  int64_t seg = segment_of(tile);
+  int64_t seg = segment_of(w.tile);
   if constexpr (PF) {
-    load_group(xa, rg);
+    load_group(xa, w.rg);
     transform_segment(xb[0], seg);
     // cur holds unit u's spectra on entry; nxt is free and receives unit u+1's
     auto unit = [&](float2 (&cur)[NF][16], float2 (&nxt)[NF][16], int64_t u) {
-      if (rg == KG) {  // next tile: new segments, one forward transform each
-        rg = 0;
-        ++tile;
-        seg = segment_of(tile);
+      if (w.tile_done(KG)) {  // next tile: new segments, one forward transform each
+        w.next_tile();
+        seg = segment_of(w.tile);
         transform_segment(nxt[0], seg);
       }
       inverse_of_products<N, NF>(cur, A, lds, par, tw, grp, g);
-      if (u + 1 < u1) load_group(nxt, rg + 1 == KG ? 0 : rg + 1);
+      if (u + 1 < u1) load_group(nxt, w.next_group(KG));
       __builtin_amdgcn_sched_barrier(0);  // keep those loads ahead of the stores
-      store_group(cur, rg, seg);
-      ++rg;
+      store_group(cur, w.rg, seg);
+      w.leave();
     };
     int64_t u = u0;
     for (; u + 1 < u1; u += 2) {
@@ -351,16 +349,15 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
   } else {
     transform_segment(xa[0], seg);
     for (int64_t u = u0; u < u1; ++u) {
-      if (rg == KG) {
-        rg = 0;
-        ++tile;
-        seg = segment_of(tile);
+      if (w.tile_done(KG)) {
+        w.next_tile();
+        seg = segment_of(w.tile);
         transform_segment(xa[0], seg);
       }
-      load_group(xa, rg);
+      load_group(xa, w.rg);
       inverse_of_products<N, NF>(xa, A, lds, par, tw, grp, g);
-      store_group(xa, rg, seg);
-      ++rg;
+      store_group(xa, w.rg, seg);
+      w.leave();
     }
   }
 }

@@ -719,6 +719,24 @@ OLS_HD int64_t batch_workgroup_order(int64_t blk, int64_t P) {
 constexpr int DH_CHUNK = 16;
 OLS_HD int64_t dh_chunks(int64_t nslots) { return (nslots + DH_CHUNK - 1) / DH_CHUNK; }
 
+// Walk of one workgroup over its units [u0, u1) of a single signal: unit u is
+// filter group u mod KG of tile u / KG (a tile's groups in order, then the
+// next tile).  The forward kernels and the host emulator both walk with it.
+struct UnitWalk {
+  int64_t tile;
+  int rg;  // filter group within the tile; KG once the tile is done
+  OLS_HD UnitWalk(int64_t u0, int KG) : tile(u0 / KG), rg((int)(u0 - (u0 / KG) * KG)) {}
+  // At the start of a unit: past the tile's last group the unit starts the
+  // next tile (new segments to transform).
+  OLS_HD bool tile_done(int KG) const { return rg == KG; }
+  OLS_HD void next_tile() {
+    rg = 0;
+    ++tile;
+  }
+  OLS_HD int next_group(int KG) const { return rg + 1 == KG ? 0 : rg + 1; }  // group of the unit after this one
+  OLS_HD void leave() { ++rg; }
+};
+
 // Partition arithmetic shared by the persistent kernels: workgroup b of P
 // owns units [first_unit(b), first_unit(b+1)); owner(u) inverts it.
 OLS_HD int64_t first_unit(int64_t U, int64_t P, int64_t b) { return U * b / P; }
