@@ -116,9 +116,12 @@ std::vector<std::array<float2, Geo<N>::TWR>> lane_twiddles(const std::vector<flo
 }
 
 // Filter spectra in kernel order F[K][8][G][2] (as the device plan stores them).
+// shift_y set: filter r delayed by row_shift(shift_y, shift_ns, shift_d, r)
+// samples (batched rows off the 64-byte grid).
 template <int N>
 std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<float2>& table, bool* guards,
-                            bool diff = false, bool real = false) {
+                            bool diff = false, bool real = false, const void* shift_y = nullptr,
+                            int64_t shift_ns = 0, int shift_d = 0) {
   using GE = Geo<N>;
   auto tw = lane_twiddles<N>(table);
   std::vector<float2> F((size_t)K * N);
@@ -135,6 +138,7 @@ std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<flo
       const int64_t row = (int64_t)(valid ? r : 0) * M;
       if (real) load_filter_real<N>(x, reinterpret_cast<const float*>(h) + row, M, valid, diff, g);
       else if (diff) load_filter_diff<N>(x, h + row, M, valid, g);
+      else if (shift_y) load_filter<N>(x, h + row, M, valid, g, row_shift(shift_y, shift_ns, shift_d, r));
       else load_filter<N>(x, h + row, M, valid, g);
     }
     fwd_from<N, 0>(xs, G, tw);
@@ -153,7 +157,7 @@ std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<flo
 template <int N>
 void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int K, int D, int H, int64_t u0,
                    int64_t u1, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw, int NF = 1,
-                   bool power = false, bool real = false, const Stencil* st = nullptr) {
+                   bool power = false, bool real = false, const Stencil* st = nullptr, bool shifted = false) {
   using GE = Geo<N>;
   const int KG = (K + NF - 1) / NF;
   std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
@@ -214,7 +218,7 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
         if (real && power) store_valid_pair<N, true>(x, yr, Ns, seg * 2 * H, D, H, g);
         else if (real) store_valid_pair<N, false>(x, yr, Ns, seg * 2 * H, D, H, g);
         else if (power) store_valid_power<N>(x, yr, Ns, seg * H, D, H, g);
-        else store_valid<N>(x, y + (int64_t)r * Ns, Ns, seg * H, D, H, g);
+        else store_valid<N>(x, y + (int64_t)r * Ns, Ns, seg * H, shifted ? D + row_shift(y, Ns, D, r) : D, H, g);
       }
     }
     w.leave();
@@ -374,6 +378,7 @@ struct EmuItem {
   std::vector<float2> F;
   int64_t Ns, unit_begin, units, tile_begin = 0, ntiles = 0;
   int K, M, N, D, H, nf;
+  bool shifted = false;
 };
 
 template <int N>
@@ -383,7 +388,8 @@ struct RangeN {
     static thread_local Group<N>* G = nullptr;
     if (!G) { G = new Group<N>(); G->poison(); }
     auto tw = lane_twiddles<N>(build_twiddles<N>());
-    forward_range<N>(it.s, it.Ns, it.F.data(), it.y, it.K, it.D, it.H, a, b, *G, tw, it.nf);
+    forward_range<N>(it.s, it.Ns, it.F.data(), it.y, it.K, it.D, it.H, a, b, *G, tw, it.nf, false, false, nullptr,
+                     it.shifted);
     return G->guards_ok() ? 0 : 3;
   }
 };
@@ -392,7 +398,8 @@ struct SpecN {
   static int run(EmuItem* itp, const float2* h) {
     EmuItem& it = *itp;
     bool guards = true;
-    it.F = spectra<N>(h, it.K, it.M, build_twiddles<N>(), &guards);
+    it.F = spectra<N>(h, it.K, it.M, build_twiddles<N>(), &guards, false, false, it.shifted ? it.y : nullptr, it.Ns,
+                      it.D);
     return guards ? 0 : 2;
   }
 };
@@ -593,6 +600,16 @@ int ols_emu_stencil_delay(int N, int Meff, int L, int R) { return ols::stencil_d
 // Default hop of such a plan.
 int ols_emu_stencil_hop(int N, int D, int R) { return ols::stencil_hop(N, D, R); }
 
+// Batched geometry for an item with output y and N_s samples: out[0] = D,
+// out[1] = H, out[2] = 1 if its filters are delayed per row (rows off the
+// 64-byte grid); and the delay of row r.
+void ols_emu_batch_geometry(int N, int M, const void* y, int64_t Ns, int32_t* out) {
+  out[0] = ols::default_delay(N, M);
+  out[2] = ols::batch_item_shifted(y, Ns, N, out[0]) ? 1 : 0;
+  out[1] = ols::batch_item_hop(N, out[0], out[2] != 0);
+}
+int ols_emu_row_shift(const void* y, int64_t Ns, int D, int r) { return ols::row_shift(y, Ns, D, r); }
+
 // Adjoint through the kernel dataflow: ds[N_s], dh[K][M].
 int ols_emu_backward(int N, const float* s, int64_t Ns, const float* gy, const float* h, int K, int M, int D, int H,
                      int grid, float* ds, float* dh) {
@@ -601,7 +618,9 @@ int ols_emu_backward(int N, const float* s, int64_t Ns, const float* gy, const f
 }
 
 // Batched forward through the kernel dataflow.  Per item: s, y (host), N_s,
-// K, M, N (must be given, 256..4096), D, H.  grid = persistent workgroups.
+// K, M, N (must be given, 256..4096), D, H; H = 0 takes the library's
+// geometry (default delay, and the row shift of rows off the 64-byte grid).
+// grid = persistent workgroups.
 int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t* Ns, const float* const* h,
                     const int* K, const int* M, const int* N, const int* D, const int* H, int grid) {
   using namespace ols::emu;
@@ -615,8 +634,14 @@ int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t
     it.K = K[i];
     it.M = M[i];
     it.N = N[i];
-    it.D = D[i];
-    it.H = H[i];
+    if (H[i] == 0) {
+      it.D = ols::default_delay(it.N, it.M);
+      it.shifted = ols::batch_item_shifted(it.y, it.Ns, it.N, it.D);
+      it.H = ols::batch_item_hop(it.N, it.D, it.shifted);
+    } else {
+      it.D = D[i];
+      it.H = H[i];
+    }
     it.nf = ols::choose_nf_batched(it.N, it.K);
     const int segs = 4096 / it.N;
     const int64_t nseg = (it.Ns + it.H - 1) / it.H;

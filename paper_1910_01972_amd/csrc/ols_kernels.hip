@@ -132,10 +132,13 @@ __device__ __forceinline__ void inverse_of_products(float2 (&x)[NF][16], const f
 // ---------------------------------------------------------------------------
 // Filters r0 .. r0 + SEGS - 1 (those < K) of one filter bank, one transform
 // per G lanes; the body of the plan step and of the batch setup.
+// With shift_y set, filter r is delayed by row_shift(shift_y, shift_ns,
+// shift_d, r) samples (batched items whose rows are off the 64-byte grid).
 template <int N>
 __device__ __forceinline__ void filter_spectra_block(const void* __restrict__ h, int K, int M, float2* __restrict__ F,
                                                      const float2* __restrict__ twt, int diff, int real, int r0,
-                                                     float2* lds) {
+                                                     float2* lds, const void* shift_y = nullptr,
+                                                     int64_t shift_ns = 0, int shift_d = 0) {
   using GE = Geo<N>;
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
@@ -148,6 +151,7 @@ __device__ __forceinline__ void filter_spectra_block(const void* __restrict__ h,
   const int64_t row = (int64_t)(valid ? r : 0) * M;
   if (real) load_filter_real<N>(x, (const float*)h + row, M, valid, diff != 0, g);
   else if (diff) load_filter_diff<N>(x, (const float2*)h + row, M, valid, g);
+  else if (shift_y) load_filter<N>(x, (const float2*)h + row, M, valid, g, row_shift(shift_y, shift_ns, shift_d, r));
   else load_filter<N>(x, (const float2*)h + row, M, valid, g);
   fwd_from<N, 0>(x, lds, par, tw, grp, g);
   if (valid) store_spectrum<N>(x, F, r, g, 1.0f / (float)N);
@@ -215,12 +219,15 @@ constexpr int forward_lds() {
 
 // STAGE: the outputs go through the non-local stencil stage (st) instead of
 // the plain store; the output rows then hold st->J * N_s elements.
+// SHIFT: with shifted set, filter r's spectrum carries a delay of
+// row_shift(yv, Ns, D, r) samples (batched rows off the 64-byte grid), and
+// row r's kept positions start that much later.
 template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE,
-          bool PF = prefetch_spectra<N, NF>(), bool STAGE = false>
+          bool PF = prefetch_spectra<N, NF>(), bool STAGE = false, bool SHIFT = false>
 __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2 (&tw)[Geo<N>::TWR], int64_t u0, int64_t u1, float2* lds,
-                                              int& par, const Stencil* st = nullptr) {
+                                              int& par, const Stencil* st = nullptr, bool shifted = false) {
   using GE = Geo<N>;
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
@@ -317,6 +324,9 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
           store_valid_pair<N, POWER, SMODE>(x[f], y_r + (int64_t)r * Ns, Ns, sg * step, D, H, g);
         else if constexpr (POWER)
           store_valid_power<N, SMODE>(x[f], y_r + (int64_t)r * Ns, Ns, sg * step, D, H, g);
+        else if constexpr (SHIFT)
+          store_valid<N, SMODE>(x[f], y_c + (int64_t)r * Ns, Ns, sg * step, shifted ? D + row_shift(yv, Ns, D, r) : D,
+                                H, g);
         else
           store_valid<N, SMODE>(x[f], y_c + (int64_t)r * Ns, Ns, sg * step, D, H, g);
       }
@@ -427,6 +437,8 @@ struct BatchItem {
   int32_t K, M, N, D, H, nf;
   int64_t tile_begin;  // first tile of this item in the batch's tile list
   int64_t ntiles;      // tiles of this item (units = ntiles * units per tile)
+  int32_t shifted;     // rows off the 64-byte grid: filters delayed by row_shift
+  int32_t pad;
 };
 
 // Values the batch setup computes on the device: totals over all items and
@@ -502,7 +514,7 @@ __device__ void device_twiddles(float2* __restrict__ out) {
 }
 
 struct ItemShape {
-  int N, nf, cls;
+  int N, nf, cls, D, H, shifted;
   int64_t ntiles, units, spec, tasks;
 };
 
@@ -511,7 +523,10 @@ __device__ __forceinline__ ItemShape item_shape(const ols_batch_item_t& it, int 
   r.N = N;
   r.nf = choose_nf_batched(N, it.K);
   r.cls = batch_class(N, r.nf);
-  const int H = N - default_delay(N, it.M);
+  r.D = default_delay(N, it.M);
+  r.shifted = batch_item_shifted(it.y, it.N_s, N, r.D) ? 1 : 0;
+  r.H = batch_item_hop(N, r.D, r.shifted != 0);
+  const int H = r.H;
   const int segs = 4096 / N;  // transforms per 256-thread workgroup
   const int64_t nseg = (it.N_s + H - 1) / H;
   r.ntiles = (nseg + segs - 1) / segs;
@@ -596,8 +611,10 @@ __global__ __launch_bounds__(SETUP_THREADS) void ols_batch_setup_kernel(const ol
     b.K = it.K;
     b.M = it.M;
     b.N = N;
-    b.D = default_delay(N, it.M);
-    b.H = N - b.D;
+    b.D = sh_.D;
+    b.H = sh_.H;
+    b.shifted = sh_.shifted;
+    b.pad = 0;
     b.nf = sh_.nf;
     b.tile_begin = 0;
     b.ntiles = sh_.ntiles;
@@ -655,7 +672,8 @@ __global__ __launch_bounds__(SETUP_THREADS) void ols_batch_setup_kernel(const ol
 template <int N>
 __device__ __attribute__((noinline)) void batch_spectra_task(const BatchItem& it, const float2* __restrict__ twt,
                                                               int r0, float2* lds) {
-  filter_spectra_block<N>(it.h, it.K, it.M, (float2*)it.spectra, twt, 0, 0, r0, lds);
+  filter_spectra_block<N>(it.h, it.K, it.M, (float2*)it.spectra, twt, 0, 0, r0, lds, it.shifted ? it.y : nullptr,
+                          it.Ns, it.D);
 }
 
 // Filter spectra of every item: task tau is one workgroup's filters of one
@@ -727,6 +745,7 @@ __device__ __forceinline__ BatchItem read_item(gptr<const BatchItem> items, int 
   r.nf = __builtin_amdgcn_readfirstlane(items[i].nf);
   r.tile_begin = wave_uniform64(items[i].tile_begin);
   r.ntiles = wave_uniform64(items[i].ntiles);
+  r.shifted = __builtin_amdgcn_readfirstlane(items[i].shifted);
   return r;
 }
 
@@ -753,8 +772,8 @@ __device__ __attribute__((noinline)) BatchWalk batched_run(const BatchItem* __re
     const BatchItem it = read_item(items, i);
     const int64_t per_tile = it.units / it.ntiles;
     const int64_t a = (t - it.tile_begin) * per_tile;
-    forward_units<N, NF, false, false, STORE_NT_WHOLE>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a,
-                                                       a + per_tile, lds, par);
+    forward_units<N, NF, false, false, STORE_NT_WHOLE, prefetch_spectra<N, NF>(), false, true>(
+        it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a, a + per_tile, lds, par, nullptr, it.shifted != 0);
     t = next_batch_tile(t, P);
     if (t >= total_tiles) return BatchWalk{t, i, par};
     // t grows, so the item walk only moves forward (items without tiles are skipped)

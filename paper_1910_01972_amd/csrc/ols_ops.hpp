@@ -27,13 +27,14 @@ OLS_HD void load_segment(float2 (&x)[16], P __restrict__ s, int64_t Ns, int64_t 
 }
 
 // Filter r zero padded to N (plan step, Fig. 1 / Alg. 2): register reg of
-// lane g receives tap g + time_pos_const(reg) if it is < M.
+// lane g receives tap g + time_pos_const(reg) - shift if that is in [0, M)
+// (shift > 0 delays the filter by that many samples; see row_shift).
 template <int N>
-OLS_HD void load_filter(float2 (&x)[16], const float2* __restrict__ h, int M, bool valid, int g) {
+OLS_HD void load_filter(float2 (&x)[16], const float2* __restrict__ h, int M, bool valid, int g, int shift = 0) {
 #pragma unroll
   for (int reg = 0; reg < 16; ++reg) {
-    const int p = g + time_pos_const<N>(reg);
-    x[reg] = (valid && p < M) ? h[p] : make_float2(0.f, 0.f);
+    const int p = g + time_pos_const<N>(reg) - shift;
+    x[reg] = (valid && p >= 0 && p < M) ? h[p] : make_float2(0.f, 0.f);
   }
 }
 
@@ -688,6 +689,30 @@ OLS_HD int batch_item_check(const void* s, int64_t Ns, const void* h, int K, int
   if (M > n) return 1;
   *N_out = n;
   return 0;
+}
+
+// Batched output rows off the 64-byte grid.  A row of complex outputs that
+// starts off the grid (y not 64-byte aligned, or N_s not a multiple of 8 for
+// rows after the first) would have every store instruction's run of
+// consecutive outputs straddle two partial granules.  For such an item each
+// filter r is delayed by row_shift samples in its spectrum, which moves row
+// r's outputs that many circular positions later: with segment starts on the
+// 8-sample grid (D and the hop multiples of 8), every store instruction then
+// starts on a granule, and only the two ends of each segment's kept window
+// are partial.  The kept positions move with the filter (D + shift), so the
+// hop leaves room for a 7-sample shift.
+OLS_HD bool rows_off_grid(const void* y, int64_t Ns) { return ((uintptr_t)y & 63) != 0 || (Ns & 7) != 0; }
+OLS_HD int shifted_hop(int N, int D) { return (N - D - 7) & ~7; }
+OLS_HD bool batch_item_shifted(const void* y, int64_t Ns, int N, int D) {
+  return rows_off_grid(y, Ns) && (D & 7) == 0 && shifted_hop(N, D) >= 8;
+}
+OLS_HD int batch_item_hop(int N, int D, bool shifted) { return shifted ? shifted_hop(N, D) : N - D; }
+// Delay of row r, 0 .. 7: output n of row r sits at element r*N_s + n of y,
+// and circular position p of segment j holds n = j*H - D + p - shift, so the
+// granule phase of a position p on the 8-sample grid is (y/8 + r*N_s - D -
+// shift) mod 8, which this shift makes 0.
+OLS_HD int row_shift(const void* y, int64_t Ns, int D, int r) {
+  return (int)((((uintptr_t)y >> 3) + (uint64_t)r * (uint64_t)Ns - (uint64_t)D) & 7);
 }
 
 // Classes of batched items, (N, filters per unit): the kernel takes the items

@@ -37,6 +37,10 @@ def emu() -> ctypes.CDLL:
         L.ols_emu_stencil_delay.restype = I32
         L.ols_emu_stencil_hop.argtypes = [I32, I32, I32]
         L.ols_emu_stencil_hop.restype = I32
+        L.ols_emu_batch_geometry.argtypes = [I32, I32, P, I64, P]
+        L.ols_emu_batch_geometry.restype = None
+        L.ols_emu_row_shift.argtypes = [P, I64, I32, I32]
+        L.ols_emu_row_shift.restype = I32
         L.ols_emu_cost_model.argtypes = [I32, I32, I32]
         L.ols_emu_cost_model.restype = I32
         for f in (L.ols_emu_forward, L.ols_emu_spectra, L.ols_emu_lds_report, L.ols_emu_geometry):
@@ -184,10 +188,24 @@ def backward(s: np.ndarray, gy: np.ndarray, h: np.ndarray, N: int, D: int, H: in
     return dsbuf[guard:guard + Ns].copy(), dh, ok
 
 
+def batch_geometry(N: int, M: int, y_addr: int, Ns: int) -> dict:
+    """The batched plan's D, H and row-shift choice for an item (the setup
+    kernel's rule)."""
+    out = (ctypes.c_int32 * 3)()
+    emu().ols_emu_batch_geometry(N, M, ctypes.c_void_p(y_addr), Ns, out)
+    return {"D": out[0], "H": out[1], "shifted": bool(out[2])}
+
+
+def row_shift(y_addr: int, Ns: int, D: int, r: int) -> int:
+    return int(emu().ols_emu_row_shift(ctypes.c_void_p(y_addr), Ns, D, r))
+
+
 def batched(items, grid: int):
     """items: list of dicts with s (complex64 [N_s]), h (complex64 [K][M]), N,
-    D, H.  Returns the list of outputs y_i [K_i][N_i_s] (NaN-prefilled, so an
-    unwritten output stays NaN)."""
+    D, H (H = 0: the library's geometry, including the row shift of outputs
+    off the 64-byte grid) and optionally y_offset (complex elements past a
+    64-byte aligned address).  Returns the list of outputs y_i [K_i][N_i_s]
+    (NaN-prefilled, so an unwritten output stays NaN)."""
     L = emu()
     L.ols_emu_batched.restype = ctypes.c_int
     n = len(items)
@@ -205,8 +223,12 @@ def batched(items, grid: int):
     for i, it in enumerate(items):
         s = np.ascontiguousarray(it["s"], dtype=np.complex64)
         h = np.ascontiguousarray(it["h"], dtype=np.complex64)
-        y = np.full((h.shape[0], s.shape[0]), np.complex64(complex(np.nan, np.nan)), dtype=np.complex64)
-        keep += [s, h, y]
+        n_y = h.shape[0] * s.shape[0]
+        off = int(it.get("y_offset", 0))
+        raw = np.full(n_y + off + 8, np.complex64(complex(np.nan, np.nan)), dtype=np.complex64)
+        base = (-(raw.ctypes.data // 8)) % 8  # elements to the next 64-byte boundary
+        y = raw[base + off:base + off + n_y].reshape(h.shape[0], s.shape[0])
+        keep += [s, h, raw]
         outs.append(y)
         S[i], Y[i], Hp[i] = s.ctypes.data, y.ctypes.data, h.ctypes.data
         Ns[i], K[i], M[i] = s.shape[0], h.shape[0], h.shape[1]

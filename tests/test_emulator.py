@@ -392,3 +392,44 @@ def test_stencil_delay_rule():
     for N, D, R in ((2048, 256, 2), (2048, 256, 0), (256, 250, 3), (256, 240, 1), (8192, 8184, 7)):
         H = emu.stencil_hop(N, D, R)
         assert 1 <= H <= N - D - R and (H % 16 == 0 or H < 16) and N - D - R - H < 16
+
+
+def test_batched_row_shift_geometry():
+    """Rows off the 64-byte grid: the setup's rule delays filter r by
+    row_shift samples, which puts the first output of every store run (circular
+    positions on the 8-sample grid) on a granule boundary, for every row and
+    segment; aligned rows keep the plain geometry."""
+    for N, M in ((256, 40), (1024, 100), (2048, 513), (4096, 300)):
+        for Ns in (8000, 8001, 8003, 8007):
+            for y_off in (0, 1, 3, 7):
+                y_addr = 1 << 20 | (y_off * 8)
+                geo = emu.batch_geometry(N, M, y_addr, Ns)
+                D, H = geo["D"], geo["H"]
+                aligned = y_off == 0 and Ns % 8 == 0
+                assert geo["shifted"] == (not aligned)
+                if aligned:
+                    assert H == N - D
+                    continue
+                assert H % 8 == 0 and D + 7 + H <= N and H >= N - D - 15
+                for r in range(5):
+                    dr = emu.row_shift(y_addr, Ns, D, r)
+                    assert 0 <= dr <= 7
+                    for j in (0, 1, 5):
+                        first = j * H - D + 0 - dr  # output at circular position 0 of segment j
+                        assert (y_addr // 8 + r * Ns + first) % 8 == 0, (N, M, Ns, y_off, r, j)
+
+
+def test_batched_row_shift_vs_oracle():
+    """The library's batched geometry with outputs off the 64-byte grid (odd
+    N_s, misaligned y): delayed spectra and per-row kept windows give eq. (1)."""
+    specs = [(5001, 3, 40, 256, 1), (4003, 2, 30, 512, 0), (20001, 2, 100, 1024, 5), (9003, 4, 513, 2048, 3),
+             (30001, 2, 300, 4096, 7), (8000, 3, 64, 1024, 2), (8000, 2, 64, 2048, 0), (7, 2, 3, 256, 4)]
+    items = []
+    for i, (Ns, K, M, N, off) in enumerate(specs):
+        s, h = workloads.make_signal_filters(Ns, K, M, seed=60 + i)
+        items.append(dict(s=s, h=h, N=N, D=0, H=0, y_offset=off))
+    for grid in (1, 5, 64):
+        outs = emu.batched(items, grid)
+        for it, y in zip(items, outs):
+            assert not np.isnan(y).any()
+            assert np.all(_rel(y, conv.direct_conv(it["s"], it["h"])) <= 1e-5)
