@@ -116,12 +116,14 @@ std::vector<std::array<float2, Geo<N>::TWR>> lane_twiddles(const std::vector<flo
 }
 
 // Filter spectra in kernel order F[K][8][G][2] (as the device plan stores them).
-// shift_y set: filter r delayed by row_shift(shift_y, shift_ns, shift_d, r)
-// samples (batched rows off the 64-byte grid).
+// shift_mask != 0: filter r delayed by row_delay(shift_y, shift_el, shift_ns,
+// shift_d, r, shift_mask) samples (output rows off the 64-byte grid), here by
+// placing its taps later (the device plan multiplies its spectra by the
+// phase of the delay instead).
 template <int N>
 std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<float2>& table, bool* guards,
-                            bool diff = false, bool real = false, const void* shift_y = nullptr,
-                            int64_t shift_ns = 0, int shift_d = 0) {
+                            bool diff = false, bool real = false, const void* shift_y = nullptr, int shift_el = 8,
+                            int64_t shift_ns = 0, int shift_d = 0, int shift_mask = 0) {
   using GE = Geo<N>;
   auto tw = lane_twiddles<N>(table);
   std::vector<float2> F((size_t)K * N);
@@ -136,10 +138,10 @@ std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<flo
       const bool valid = r < K;
       float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
       const int64_t row = (int64_t)(valid ? r : 0) * M;
-      if (real) load_filter_real<N>(x, reinterpret_cast<const float*>(h) + row, M, valid, diff, g);
-      else if (diff) load_filter_diff<N>(x, h + row, M, valid, g);
-      else if (shift_y) load_filter<N>(x, h + row, M, valid, g, row_shift(shift_y, shift_ns, shift_d, r));
-      else load_filter<N>(x, h + row, M, valid, g);
+      const int delay = shift_mask ? row_delay(shift_y, shift_el, shift_ns, shift_d, r, shift_mask) : 0;
+      if (real) load_filter_real<N>(x, reinterpret_cast<const float*>(h) + row, M, valid, diff, g, delay);
+      else if (diff) load_filter_diff<N>(x, h + row, M, valid, g, delay);
+      else load_filter<N>(x, h + row, M, valid, g, delay);
     }
     fwd_from<N, 0>(xs, G, tw);
     for (int t = 0; t < GE::WG; ++t) {
@@ -157,7 +159,7 @@ std::vector<float2> spectra(const float2* h, int K, int M, const std::vector<flo
 template <int N>
 void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int K, int D, int H, int64_t u0,
                    int64_t u1, Group<N>& G, const std::vector<std::array<float2, Geo<N>::TWR>>& tw, int NF = 1,
-                   bool power = false, bool real = false, const Stencil* st = nullptr, bool shifted = false) {
+                   bool power = false, bool real = false, const Stencil* st = nullptr, int shift_mask = 0) {
   using GE = Geo<N>;
   const int KG = (K + NF - 1) / NF;
   std::vector<std::array<float2, 16>> xs(GE::WG), A(GE::WG);
@@ -215,16 +217,19 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
         const int64_t seg = w.tile * GE::SEGS + grp;
         const float2(&x)[16] = *reinterpret_cast<float2(*)[16]>(xs[t].data());
         float* yr = reinterpret_cast<float*>(y) + (int64_t)r * Ns;
-        if (real && power) store_valid_pair<N, true>(x, yr, Ns, seg * 2 * H, D, H, g);
-        else if (real) store_valid_pair<N, false>(x, yr, Ns, seg * 2 * H, D, H, g);
-        else if (power) store_valid_power<N>(x, yr, Ns, seg * H, D, H, g);
-        else store_valid<N>(x, y + (int64_t)r * Ns, Ns, seg * H, shifted ? D + row_shift(y, Ns, D, r) : D, H, g);
+        const int Dr = D + row_delay(y, (real || power) ? 4 : 8, Ns, D, r, shift_mask);
+        if (real && power) store_valid_pair<N, true>(x, yr, Ns, seg * 2 * H, Dr, H, g);
+        else if (real) store_valid_pair<N, false>(x, yr, Ns, seg * 2 * H, Dr, H, g);
+        else if (power) store_valid_power<N>(x, yr, Ns, seg * H, Dr, H, g);
+        else store_valid<N>(x, y + (int64_t)r * Ns, Ns, seg * H, Dr, H, g);
       }
     }
     w.leave();
   }
 }
 
+// post & 8: the library's treatment of output rows off the 64-byte grid
+// (row_shift_geometry on the given D and H; delayed filters).
 template <int N>
 int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y,
             int post = 0, const Stencil* st = nullptr) {
@@ -232,7 +237,11 @@ int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, i
   const std::vector<float2> table = build_twiddles<N>();
   bool guards = true;
   const bool real = (post & 4) != 0;
-  const std::vector<float2> F = spectra<N>(h, K, M, table, &guards, (post & 1) != 0, real);
+  const int el = (post & 6) ? 4 : 8;
+  RowShift rs{H, 0};
+  if ((post & 8) && !st) rs = row_shift_geometry(y, Ns, N, D, H, el, true);
+  H = rs.H;
+  const std::vector<float2> F = spectra<N>(h, K, M, table, &guards, (post & 1) != 0, real, y, el, Ns, D, rs.mask);
   if (!guards) return 2;
   auto tw = lane_twiddles<N>(table);
   const int nf = real ? choose_nf_real(N, K) : choose_nf(N, K);
@@ -245,7 +254,7 @@ int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, i
   G.poison();
   for (int b = 0; b < grid; ++b) {
     const int64_t u0 = first_unit(U, grid, b), u1 = first_unit(U, grid, b + 1);
-    if (u0 < u1) forward_range<N>(s, Ns, F.data(), y, K, D, H, u0, u1, G, tw, nf, (post & 2) != 0, real, st);
+    if (u0 < u1) forward_range<N>(s, Ns, F.data(), y, K, D, H, u0, u1, G, tw, nf, (post & 2) != 0, real, st, rs.mask);
   }
   return G.guards_ok() ? 0 : 3;
 }
@@ -378,7 +387,7 @@ struct EmuItem {
   std::vector<float2> F;
   int64_t Ns, unit_begin, units, tile_begin = 0, ntiles = 0;
   int K, M, N, D, H, nf;
-  bool shifted = false;
+  int shift_mask = 0;
 };
 
 template <int N>
@@ -389,7 +398,7 @@ struct RangeN {
     if (!G) { G = new Group<N>(); G->poison(); }
     auto tw = lane_twiddles<N>(build_twiddles<N>());
     forward_range<N>(it.s, it.Ns, it.F.data(), it.y, it.K, it.D, it.H, a, b, *G, tw, it.nf, false, false, nullptr,
-                     it.shifted);
+                     it.shift_mask);
     return G->guards_ok() ? 0 : 3;
   }
 };
@@ -398,8 +407,8 @@ struct SpecN {
   static int run(EmuItem* itp, const float2* h) {
     EmuItem& it = *itp;
     bool guards = true;
-    it.F = spectra<N>(h, it.K, it.M, build_twiddles<N>(), &guards, false, false, it.shifted ? it.y : nullptr, it.Ns,
-                      it.D);
+    it.F = spectra<N>(h, it.K, it.M, build_twiddles<N>(), &guards, false, false, it.y, 8, it.Ns, it.D,
+                      it.shift_mask);
     return guards ? 0 : 2;
   }
 };
@@ -601,14 +610,23 @@ int ols_emu_stencil_delay(int N, int Meff, int L, int R) { return ols::stencil_d
 int ols_emu_stencil_hop(int N, int D, int R) { return ols::stencil_hop(N, D, R); }
 
 // Batched geometry for an item with output y and N_s samples: out[0] = D,
-// out[1] = H, out[2] = 1 if its filters are delayed per row (rows off the
-// 64-byte grid); and the delay of row r.
+// out[1] = H, out[2] = the mask of its per-row filter delays (0: rows on the
+// 128-byte grid); and the delay of row r.
 void ols_emu_batch_geometry(int N, int M, const void* y, int64_t Ns, int32_t* out) {
   out[0] = ols::default_delay(N, M);
-  out[2] = ols::batch_item_shifted(y, Ns, N, out[0]) ? 1 : 0;
-  out[1] = ols::batch_item_hop(N, out[0], out[2] != 0);
+  const ols::RowShift rs = ols::batch_row_shift(y, Ns, N, out[0]);
+  out[2] = rs.mask;
+  out[1] = rs.H;
 }
-int ols_emu_row_shift(const void* y, int64_t Ns, int D, int r) { return ols::row_shift(y, Ns, D, r); }
+int ols_emu_row_shift(const void* y, int64_t Ns, int D, int r, int mask) { return ols::row_delay(y, 8, Ns, D, r, mask); }
+
+// The single-signal forward's rule for a call: out[0] = H, out[1] = mask,
+// for outputs of el bytes (8 complex64, 4 float32) and the plan's D, H.
+void ols_emu_row_shift_geometry(const void* y, int64_t Ns, int N, int D, int H, int el, int32_t* out) {
+  const ols::RowShift rs = ols::row_shift_geometry(y, Ns, N, D, H, el, true);
+  out[0] = rs.H;
+  out[1] = rs.mask;
+}
 
 // Adjoint through the kernel dataflow: ds[N_s], dh[K][M].
 int ols_emu_backward(int N, const float* s, int64_t Ns, const float* gy, const float* h, int K, int M, int D, int H,
@@ -636,8 +654,9 @@ int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t
     it.N = N[i];
     if (H[i] == 0) {
       it.D = ols::default_delay(it.N, it.M);
-      it.shifted = ols::batch_item_shifted(it.y, it.Ns, it.N, it.D);
-      it.H = ols::batch_item_hop(it.N, it.D, it.shifted);
+      const ols::RowShift rs = ols::batch_row_shift(it.y, it.Ns, it.N, it.D);
+      it.shift_mask = rs.mask;
+      it.H = rs.H;
     } else {
       it.D = D[i];
       it.H = H[i];

@@ -132,13 +132,18 @@ __device__ __forceinline__ void inverse_of_products(float2 (&x)[NF][16], const f
 // ---------------------------------------------------------------------------
 // Filters r0 .. r0 + SEGS - 1 (those < K) of one filter bank, one transform
 // per G lanes; the body of the plan step and of the batch setup.
-// With shift_y set, filter r is delayed by row_shift(shift_y, shift_ns,
-// shift_d, r) samples (batched items whose rows are off the 64-byte grid).
+// RowShift: with mask != 0, filter r is delayed by row_delay(y, el, Ns, D,
+// r, mask) samples (output rows off the 64-byte grid).
+struct SpectraShift {
+  const void* y;
+  int64_t Ns;
+  int el, D, mask;
+};
+
 template <int N>
 __device__ __forceinline__ void filter_spectra_block(const void* __restrict__ h, int K, int M, float2* __restrict__ F,
                                                      const float2* __restrict__ twt, int diff, int real, int r0,
-                                                     float2* lds, const void* shift_y = nullptr,
-                                                     int64_t shift_ns = 0, int shift_d = 0) {
+                                                     float2* lds, const SpectraShift sh = SpectraShift{}) {
   using GE = Geo<N>;
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
@@ -149,10 +154,10 @@ __device__ __forceinline__ void filter_spectra_block(const void* __restrict__ h,
   float2 x[16];
   const bool valid = r < K;
   const int64_t row = (int64_t)(valid ? r : 0) * M;
-  if (real) load_filter_real<N>(x, (const float*)h + row, M, valid, diff != 0, g);
-  else if (diff) load_filter_diff<N>(x, (const float2*)h + row, M, valid, g);
-  else if (shift_y) load_filter<N>(x, (const float2*)h + row, M, valid, g, row_shift(shift_y, shift_ns, shift_d, r));
-  else load_filter<N>(x, (const float2*)h + row, M, valid, g);
+  const int delay = sh.mask ? row_delay(sh.y, sh.el, sh.Ns, sh.D, r, sh.mask) : 0;
+  if (real) load_filter_real<N>(x, (const float*)h + row, M, valid, diff != 0, g, delay);
+  else if (diff) load_filter_diff<N>(x, (const float2*)h + row, M, valid, g, delay);
+  else load_filter<N>(x, (const float2*)h + row, M, valid, g, delay);
   fwd_from<N, 0>(x, lds, par, tw, grp, g);
   if (valid) store_spectrum<N>(x, F, r, g, 1.0f / (float)N);
 }
@@ -161,9 +166,9 @@ template <int N>
 __global__ __launch_bounds__(Geo<N>::WG) void ols_filter_spectra_kernel(const void* __restrict__ h, int K, int M,
                                                                         float2* __restrict__ F,
                                                                         const float2* __restrict__ twt, int diff,
-                                                                        int real) {
+                                                                        int real, const SpectraShift sh) {
   __shared__ float2 lds[2 * Geo<N>::LDS];
-  filter_spectra_block<N>(h, K, M, F, twt, diff, real, blockIdx.x * Geo<N>::SEGS, lds);
+  filter_spectra_block<N>(h, K, M, F, twt, diff, real, blockIdx.x * Geo<N>::SEGS, lds, sh);
 }
 
 // Natural-order copy of the spectra: out[r][k] = F[r][spectrum_offset(reg, g)]
@@ -177,6 +182,27 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
   const int pair = rem >> 1, j = pair / Geo<N>::G, g = pair - j * Geo<N>::G;
   const int reg = 2 * j + (rem & 1);
   out[(int64_t)r * N + spectrum_index<N>(g, reg)] = F[i];
+}
+
+// Filter spectra delayed per row, for output rows off the 64-byte grid:
+// out[r] = F[r] * exp(-2 pi i k d_r / N), the spectrum of filter r delayed by
+// d_r = row_delay(sh.y, sh.el, sh.Ns, sh.D, r, sh.mask) samples, in the same
+// storage order (the phase from the exact integer k * d_r mod N, in float64).
+template <int N>
+__global__ void ols_spectra_delay_kernel(const float2* __restrict__ F, int K, float2* __restrict__ out,
+                                         const SpectraShift sh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // over K * N
+  if (i >= (int64_t)K * N) return;
+  const int r = (int)(i / N);
+  const int rem = (int)(i - (int64_t)r * N);  // = spectrum_offset(reg, g)
+  const int pair = rem >> 1, j = pair / Geo<N>::G, g = pair - j * Geo<N>::G;
+  const int reg = 2 * j + (rem & 1);
+  const int k = spectrum_index<N>(g, reg);
+  const int d = row_delay(sh.y, sh.el, sh.Ns, sh.D, r, sh.mask);
+  const int m = (int)(((int64_t)k * d) % N);
+  double sn, cs;
+  sincospi(2.0 * (double)m / (double)N, &sn, &cs);
+  out[i] = cmul(F[i], make_float2((float)cs, (float)(-sn)));
 }
 
 // ---------------------------------------------------------------------------
@@ -219,15 +245,15 @@ constexpr int forward_lds() {
 
 // STAGE: the outputs go through the non-local stencil stage (st) instead of
 // the plain store; the output rows then hold st->J * N_s elements.
-// SHIFT: with shifted set, filter r's spectrum carries a delay of
-// row_shift(yv, Ns, D, r) samples (batched rows off the 64-byte grid), and
-// row r's kept positions start that much later.
+// shift_mask != 0: filter r's spectrum carries a delay of
+// row_delay(yv, el, Ns, D, r, shift_mask) samples (output rows off the
+// 64-byte grid), and row r's kept positions start that much later.
 template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE,
-          bool PF = prefetch_spectra<N, NF>(), bool STAGE = false, bool SHIFT = false>
+          bool PF = prefetch_spectra<N, NF>(), bool STAGE = false>
 __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2 (&tw)[Geo<N>::TWR], int64_t u0, int64_t u1, float2* lds,
-                                              int& par, const Stencil* st = nullptr, bool shifted = false) {
+                                              int& par, const Stencil* st = nullptr, int shift_mask = 0) {
   using GE = Geo<N>;
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
@@ -311,6 +337,7 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
       }
     }
   };
+  constexpr int EL = (REAL || POWER) ? 4 : 8;  // bytes per output sample
   auto store_group = [&](const float2 (&x)[NF][16], int q, int64_t sg) {
     if constexpr (STAGE) {
       stage_group(x, q, sg);
@@ -320,15 +347,13 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
     for (int f = 0; f < NF; ++f) {
       const int r = q * NF + f;
       if (NF == 1 || r < K) {
+        const int Dr = D + row_delay(yv, EL, Ns, D, r, shift_mask);  // first kept position of row r
         if constexpr (REAL)
-          store_valid_pair<N, POWER, SMODE>(x[f], y_r + (int64_t)r * Ns, Ns, sg * step, D, H, g);
+          store_valid_pair<N, POWER, SMODE>(x[f], y_r + (int64_t)r * Ns, Ns, sg * step, Dr, H, g);
         else if constexpr (POWER)
-          store_valid_power<N, SMODE>(x[f], y_r + (int64_t)r * Ns, Ns, sg * step, D, H, g);
-        else if constexpr (SHIFT)
-          store_valid<N, SMODE>(x[f], y_c + (int64_t)r * Ns, Ns, sg * step, shifted ? D + row_shift(yv, Ns, D, r) : D,
-                                H, g);
+          store_valid_power<N, SMODE>(x[f], y_r + (int64_t)r * Ns, Ns, sg * step, Dr, H, g);
         else
-          store_valid<N, SMODE>(x[f], y_c + (int64_t)r * Ns, Ns, sg * step, D, H, g);
+          store_valid<N, SMODE>(x[f], y_c + (int64_t)r * Ns, Ns, sg * step, Dr, H, g);
       }
     }
   };
@@ -376,26 +401,28 @@ template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STOR
 __device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2* __restrict__ twt, int64_t u0, int64_t u1, float2* lds,
-                                              int& par, const Stencil* st = nullptr) {
+                                              int& par, const Stencil* st = nullptr, int shift_mask = 0) {
   float2 tw[Geo<N>::TWR];
   load_lane_twiddles<N>(tw, twt, threadIdx.x % Geo<N>::G);
   // the stage's accumulators take the registers of the spectrum prefetch
   forward_units<N, NF, POWER, REAL, SMODE, prefetch_spectra<N, NF>() && !STAGE, STAGE>(sv, Ns, F, yv, K, D, H, tw, u0,
-                                                                                        u1, lds, par, st);
+                                                                                        u1, lds, par, st, shift_mask);
 }
 
+// shift_mask: 0, or the row shift of output rows off the 64-byte grid
+// (row_shift_geometry; F then holds the delayed filters).
 template <int N, int NF, bool POWER, bool REAL>
 __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const void* __restrict__ s, int64_t Ns,
                                                                  const float2* __restrict__ F, void* __restrict__ y,
                                                                  int K, int D, int H, int64_t ntiles,
-                                                                 const float2* __restrict__ twt) {
+                                                                 const float2* __restrict__ twt, int shift_mask) {
   __shared__ float2 lds[forward_lds<N, NF, false>()];
   const int64_t U = ntiles * ((K + NF - 1) / NF);
   const int64_t u0 = first_unit(U, gridDim.x, blockIdx.x);
   const int64_t u1 = first_unit(U, gridDim.x, blockIdx.x + 1);
   if (u0 >= u1) return;  // uniform over the workgroup
   int par = 0;
-  forward_range<N, NF, POWER, REAL>(s, Ns, F, y, K, D, H, twt, u0, u1, lds, par);
+  forward_range<N, NF, POWER, REAL>(s, Ns, F, y, K, D, H, twt, u0, u1, lds, par, nullptr, shift_mask);
 }
 
 // The forward kernel with the non-local post-processing stage (sec. 4): the
@@ -437,7 +464,7 @@ struct BatchItem {
   int32_t K, M, N, D, H, nf;
   int64_t tile_begin;  // first tile of this item in the batch's tile list
   int64_t ntiles;      // tiles of this item (units = ntiles * units per tile)
-  int32_t shifted;     // rows off the 64-byte grid: filters delayed by row_shift
+  int32_t shift_mask;  // rows off the 128-byte grid: filters delayed by row_delay with this mask
   int32_t pad;
 };
 
@@ -514,7 +541,7 @@ __device__ void device_twiddles(float2* __restrict__ out) {
 }
 
 struct ItemShape {
-  int N, nf, cls, D, H, shifted;
+  int N, nf, cls, D, H, shift_mask;
   int64_t ntiles, units, spec, tasks;
 };
 
@@ -524,8 +551,9 @@ __device__ __forceinline__ ItemShape item_shape(const ols_batch_item_t& it, int 
   r.nf = choose_nf_batched(N, it.K);
   r.cls = batch_class(N, r.nf);
   r.D = default_delay(N, it.M);
-  r.shifted = batch_item_shifted(it.y, it.N_s, N, r.D) ? 1 : 0;
-  r.H = batch_item_hop(N, r.D, r.shifted != 0);
+  const RowShift rs = batch_row_shift(it.y, it.N_s, N, r.D);
+  r.shift_mask = rs.mask;
+  r.H = rs.H;
   const int H = r.H;
   const int segs = 4096 / N;  // transforms per 256-thread workgroup
   const int64_t nseg = (it.N_s + H - 1) / H;
@@ -613,7 +641,7 @@ __global__ __launch_bounds__(SETUP_THREADS) void ols_batch_setup_kernel(const ol
     b.N = N;
     b.D = sh_.D;
     b.H = sh_.H;
-    b.shifted = sh_.shifted;
+    b.shift_mask = sh_.shift_mask;
     b.pad = 0;
     b.nf = sh_.nf;
     b.tile_begin = 0;
@@ -672,8 +700,8 @@ __global__ __launch_bounds__(SETUP_THREADS) void ols_batch_setup_kernel(const ol
 template <int N>
 __device__ __attribute__((noinline)) void batch_spectra_task(const BatchItem& it, const float2* __restrict__ twt,
                                                               int r0, float2* lds) {
-  filter_spectra_block<N>(it.h, it.K, it.M, (float2*)it.spectra, twt, 0, 0, r0, lds, it.shifted ? it.y : nullptr,
-                          it.Ns, it.D);
+  filter_spectra_block<N>(it.h, it.K, it.M, (float2*)it.spectra, twt, 0, 0, r0, lds,
+                          SpectraShift{it.y, it.Ns, 8, it.D, it.shift_mask});
 }
 
 // Filter spectra of every item: task tau is one workgroup's filters of one
@@ -745,7 +773,7 @@ __device__ __forceinline__ BatchItem read_item(gptr<const BatchItem> items, int 
   r.nf = __builtin_amdgcn_readfirstlane(items[i].nf);
   r.tile_begin = wave_uniform64(items[i].tile_begin);
   r.ntiles = wave_uniform64(items[i].ntiles);
-  r.shifted = __builtin_amdgcn_readfirstlane(items[i].shifted);
+  r.shift_mask = __builtin_amdgcn_readfirstlane(items[i].shift_mask);
   return r;
 }
 
@@ -772,8 +800,8 @@ __device__ __attribute__((noinline)) BatchWalk batched_run(const BatchItem* __re
     const BatchItem it = read_item(items, i);
     const int64_t per_tile = it.units / it.ntiles;
     const int64_t a = (t - it.tile_begin) * per_tile;
-    forward_units<N, NF, false, false, STORE_NT_WHOLE, prefetch_spectra<N, NF>(), false, true>(
-        it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a, a + per_tile, lds, par, nullptr, it.shifted != 0);
+    forward_units<N, NF, false, false, STORE_NT_WHOLE>(it.s, it.Ns, it.spectra, it.y, it.K, it.D, it.H, tw, a,
+                                                       a + per_tile, lds, par, nullptr, it.shift_mask);
     t = next_batch_tile(t, P);
     if (t >= total_tiles) return BatchWalk{t, i, par};
     // t grows, so the item walk only moves forward (items without tiles are skipped)
@@ -1234,6 +1262,7 @@ struct ols_plan_s {
   void* bwd_mem = nullptr;  // the adjoint's scratch, allocated by ols_plan_reserve_backward
   BwdWorkspace bwd{};       // carved from bwd_mem for the adjoint's full grid
   float2* spectra = nullptr;
+  float2* spectra_delayed = nullptr;  // per-row delayed copy for output rows off the 64-byte grid
   float2* twiddles = nullptr;
 };
 
@@ -1274,7 +1303,15 @@ struct Kern {
   static hipError_t spectra(const void* h, int K, int M, float2* F, const float2* tw, hipStream_t st, int diff,
                             int real) {
     const int blocks = (K + GE::SEGS - 1) / GE::SEGS;
-    hipLaunchKernelGGL(ols_filter_spectra_kernel<N>, dim3(blocks), dim3(GE::WG), 0, st, h, K, M, F, tw, diff, real);
+    hipLaunchKernelGGL(ols_filter_spectra_kernel<N>, dim3(blocks), dim3(GE::WG), 0, st, h, K, M, F, tw, diff, real,
+                       SpectraShift{});
+    return hipGetLastError();
+  }
+  static hipError_t delayed(const float2* F, int K, float2* out, const SpectraShift& sh, hipStream_t st) {
+    const int64_t total = (int64_t)K * N;
+    const int threads = 256;
+    const int64_t blocks = (total + threads - 1) / threads;
+    hipLaunchKernelGGL(ols_spectra_delay_kernel<N>, dim3((unsigned)blocks), dim3(threads), 0, st, F, K, out, sh);
     return hipGetLastError();
   }
   static hipError_t natural(const float2* F, int K, float2* out, hipStream_t st) {
@@ -1285,7 +1322,7 @@ struct Kern {
     return hipGetLastError();
   }
   // Forward kernel instance for (filters per unit, power epilogue, R2R).
-  using ForwardFn = void (*)(const void*, int64_t, const float2*, void*, int, int, int, int64_t, const float2*);
+  using ForwardFn = void (*)(const void*, int64_t, const float2*, void*, int, int, int, int64_t, const float2*, int);
   template <int NF>
   static ForwardFn forward_fn_nf(bool power, bool real) {
     if (real) {
@@ -1321,7 +1358,19 @@ struct Kern {
     return stencil_fn_nf<1>(power, real);
   }
   static hipError_t forward(const ols_plan_s* p, const void* s, int64_t Ns, void* y, hipStream_t st) {
-    const int64_t nseg = (Ns + p->H - 1) / p->H;
+    // output rows off the 64-byte grid run with per-row delayed filters (the
+    // delayed copy is rewritten on the call's stream before the forward)
+    const bool float_out = (p->flags & (OLS_REAL | OLS_POST_POWER)) != 0;
+    const RowShift rs = row_shift_geometry(y, Ns, N, p->D, p->H, float_out ? 4 : 8, !p->stencil_on);
+    const float2* F = p->spectra;
+    if (rs.mask) {
+      const hipError_t e = delayed(p->spectra, p->K, p->spectra_delayed,
+                                   SpectraShift{y, Ns, float_out ? 4 : 8, p->D, rs.mask}, st);
+      if (e != hipSuccess) return e;
+      F = p->spectra_delayed;
+    }
+    const int H = rs.H;
+    const int64_t nseg = (Ns + H - 1) / H;
     const int64_t ntrans = (p->flags & OLS_REAL) ? (nseg + 1) / 2 : nseg;  // R2R: segment pairs
     const int64_t ntiles = (ntrans + GE::SEGS - 1) / GE::SEGS;
     const int64_t units = ntiles * ((p->K + p->nf - 1) / p->nf);
@@ -1329,13 +1378,13 @@ struct Kern {
     if (p->stencil_on) {
       // J <= 2 phases go out as one element per sample when y is aligned to it
       Stencil sten = p->stencil;
-      const uintptr_t el = (uintptr_t)sten.J * (((p->flags & (OLS_REAL | OLS_POST_POWER)) != 0) ? 4 : 8);
+      const uintptr_t el = (uintptr_t)sten.J * (float_out ? 4 : 8);
       sten.packed = sten.J <= 2 && (uintptr_t)y % el == 0;
       hipLaunchKernelGGL(stencil_fn(p->nf, p->flags), dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra, y,
                          p->K, p->D, p->H, ntiles, p->twiddles, sten);
     } else
-      hipLaunchKernelGGL(forward_fn(p->nf, p->flags), dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, p->spectra,
-                         y, p->K, p->D, p->H, ntiles, p->twiddles);
+      hipLaunchKernelGGL(forward_fn(p->nf, p->flags), dim3((unsigned)grid), dim3(GE::WG), 0, st, s, Ns, F, y, p->K,
+                         p->D, H, ntiles, p->twiddles, rs.mask);
     return hipGetLastError();
   }
   static hipError_t occupancy(int nf, int flags, bool stage, int* blocks_per_cu) {
@@ -1541,6 +1590,7 @@ void destroy_plan(ols_plan_s* p) {
   if (!p) return;
   if (p->bwd_mem) (void)hipFree(p->bwd_mem);
   if (p->spectra) (void)hipFree(p->spectra);
+  if (p->spectra_delayed) (void)hipFree(p->spectra_delayed);
   if (p->twiddles) (void)hipFree(p->twiddles);
   delete p;
 }
@@ -1695,6 +1745,8 @@ ols_status_t ols_plan_ex(ols_plan_t* plan, const void* h, int32_t K, int32_t M, 
     e = hipMalloc(&p->twiddles, tw.size() * sizeof(float2));
     if (e != hipSuccess) { destroy_plan(p); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "twiddle allocation"); }
     e = hipMalloc(&p->spectra, (size_t)K * N * sizeof(float2));
+    if (e != hipSuccess) { destroy_plan(p); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "spectra allocation"); }
+    e = hipMalloc(&p->spectra_delayed, (size_t)K * N * sizeof(float2));
     if (e != hipSuccess) { destroy_plan(p); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "spectra allocation"); }
     hipStream_t st = (hipStream_t)stream;
     e = hipMemcpyAsync(p->twiddles, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, st);

@@ -43,11 +43,11 @@ OLS_HD void load_filter(float2 (&x)[16], const float2* __restrict__ h, int M, bo
 // convolved signal (sec. 4, non-local post-processing) and, being a
 // convolution, it folds into the filter spectrum at no cost per segment.
 template <int N>
-OLS_HD void load_filter_diff(float2 (&x)[16], const float2* __restrict__ h, int M, bool valid, int g) {
+OLS_HD void load_filter_diff(float2 (&x)[16], const float2* __restrict__ h, int M, bool valid, int g, int shift = 0) {
 #pragma unroll
   for (int reg = 0; reg < 16; ++reg) {
-    const int p = g + time_pos_const<N>(reg);
-    const float2 a = (valid && p < M) ? h[p] : make_float2(0.f, 0.f);
+    const int p = g + time_pos_const<N>(reg) - shift;
+    const float2 a = (valid && p >= 0 && p < M) ? h[p] : make_float2(0.f, 0.f);
     const float2 b = (valid && p >= 1 && p <= M) ? h[p - 1] : make_float2(0.f, 0.f);
     x[reg] = csub(a, b);
   }
@@ -56,11 +56,12 @@ OLS_HD void load_filter_diff(float2 (&x)[16], const float2* __restrict__ h, int 
 // Real filter r (R2R plans) as complex taps with zero imaginary part,
 // optionally followed by the first difference of load_filter_diff.
 template <int N>
-OLS_HD void load_filter_real(float2 (&x)[16], const float* __restrict__ h, int M, bool valid, bool diff, int g) {
+OLS_HD void load_filter_real(float2 (&x)[16], const float* __restrict__ h, int M, bool valid, bool diff, int g,
+                             int shift = 0) {
 #pragma unroll
   for (int reg = 0; reg < 16; ++reg) {
-    const int p = g + time_pos_const<N>(reg);
-    float a = (valid && p < M) ? h[p] : 0.f;
+    const int p = g + time_pos_const<N>(reg) - shift;
+    float a = (valid && p >= 0 && p < M) ? h[p] : 0.f;
     if (diff) a -= (valid && p >= 1 && p <= M) ? h[p - 1] : 0.f;
     x[reg] = make_float2(a, 0.f);
   }
@@ -691,28 +692,41 @@ OLS_HD int batch_item_check(const void* s, int64_t Ns, const void* h, int K, int
   return 0;
 }
 
-// Batched output rows off the 64-byte grid.  A row of complex outputs that
-// starts off the grid (y not 64-byte aligned, or N_s not a multiple of 8 for
-// rows after the first) would have every store instruction's run of
-// consecutive outputs straddle two partial granules.  For such an item each
-// filter r is delayed by row_shift samples in its spectrum, which moves row
-// r's outputs that many circular positions later: with segment starts on the
-// 8-sample grid (D and the hop multiples of 8), every store instruction then
-// starts on a granule, and only the two ends of each segment's kept window
-// are partial.  The kept positions move with the filter (D + shift), so the
-// hop leaves room for a 7-sample shift.
-OLS_HD bool rows_off_grid(const void* y, int64_t Ns) { return ((uintptr_t)y & 63) != 0 || (Ns & 7) != 0; }
-OLS_HD int shifted_hop(int N, int D) { return (N - D - 7) & ~7; }
-OLS_HD bool batch_item_shifted(const void* y, int64_t Ns, int N, int D) {
-  return rows_off_grid(y, Ns) && (D & 7) == 0 && shifted_hop(N, D) >= 8;
+// Output rows off the 128-byte grid (the L2 line).  A row that starts off
+// the grid (y not 128-byte aligned, or N_s not a multiple of LS, the outputs
+// per line: 16 complex64 or 32 float32) would have every store
+// instruction's run of consecutive outputs straddle two partly written
+// lines.  For such a call each filter r is delayed by row_delay samples in
+// its spectrum, which moves row r's outputs that many circular positions
+// later: with the hop a multiple of LS, every store instruction then starts
+// on a line (runs start at circular positions that are multiples of 64, or
+// of the transform's G lanes), and only the two ends of each segment's kept
+// window are partial.  The kept positions move with the filter (D + delay),
+// so the hop must leave room for a delay of LS - 1.
+struct RowShift {
+  int H;     // hop the call runs with
+  int mask;  // LS - 1 when the rows are shifted, else 0
+};
+constexpr int SHIFT_LINE = 128;  // bytes
+// H: the plan's hop; el: bytes per output; allowed: the kernel supports it.
+OLS_HD RowShift row_shift_geometry(const void* y, int64_t Ns, int N, int D, int H, int el, bool allowed) {
+  const int LS = SHIFT_LINE / el;
+  const bool off = ((uintptr_t)y & (SHIFT_LINE - 1)) != 0 || (Ns & (LS - 1)) != 0;
+  if (!allowed || !off) return RowShift{H, 0};
+  if ((H & (LS - 1)) == 0 && D + (LS - 1) + H <= N) return RowShift{H, LS - 1};
+  const int hs = (N - D - (LS - 1)) & ~(LS - 1);
+  return hs >= LS ? RowShift{hs, LS - 1} : RowShift{H, 0};
 }
-OLS_HD int batch_item_hop(int N, int D, bool shifted) { return shifted ? shifted_hop(N, D) : N - D; }
-// Delay of row r, 0 .. 7: output n of row r sits at element r*N_s + n of y,
-// and circular position p of segment j holds n = j*H - D + p - shift, so the
-// granule phase of a position p on the 8-sample grid is (y/8 + r*N_s - D -
-// shift) mod 8, which this shift makes 0.
-OLS_HD int row_shift(const void* y, int64_t Ns, int D, int r) {
-  return (int)((((uintptr_t)y >> 3) + (uint64_t)r * (uint64_t)Ns - (uint64_t)D) & 7);
+// Delay of row r (0 .. mask): output n of row r is element r*N_s + n of y
+// (el bytes each), and circular position p of segment j holds
+// n = j*H - D + p - delay, so the line phase of a position p on the LS-sample
+// grid is (y/el + r*N_s - D - delay) mod LS, which this delay makes 0.
+OLS_HD int row_delay(const void* y, int el, int64_t Ns, int D, int r, int mask) {
+  return (int)((((uintptr_t)y / (uintptr_t)el) + (uint64_t)r * (uint64_t)Ns - (uint64_t)D) & (uint64_t)mask);
+}
+// Batched items (complex64 rows, the default hop).
+OLS_HD RowShift batch_row_shift(const void* y, int64_t Ns, int N, int D) {
+  return row_shift_geometry(y, Ns, N, D, N - D, 8, true);
 }
 
 // Classes of batched items, (N, filters per unit): the kernel takes the items

@@ -39,7 +39,9 @@ def emu() -> ctypes.CDLL:
         L.ols_emu_stencil_hop.restype = I32
         L.ols_emu_batch_geometry.argtypes = [I32, I32, P, I64, P]
         L.ols_emu_batch_geometry.restype = None
-        L.ols_emu_row_shift.argtypes = [P, I64, I32, I32]
+        L.ols_emu_row_shift.argtypes = [P, I64, I32, I32, I32]
+        L.ols_emu_row_shift_geometry.argtypes = [P, I64, I32, I32, I32, I32, P]
+        L.ols_emu_row_shift_geometry.restype = None
         L.ols_emu_row_shift.restype = I32
         L.ols_emu_cost_model.argtypes = [I32, I32, I32]
         L.ols_emu_cost_model.restype = I32
@@ -109,10 +111,13 @@ def forward(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, gua
     return y, s_guard_ok, y_guard_ok
 
 
-def forward_post(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, post: int, guard: int = 4096):
+def forward_post(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, post: int, guard: int = 4096,
+                 y_offset: int = 0):
     """Forward OLS with flags (1 derivative, 2 power, 4 R2R with float32 s, h
-    and y); the output is complex64 [K][N_s], or float32 for power and R2R,
-    inside NaN guard bands.  Returns (y, y_guard_ok)."""
+    and y, 8 the library's row shift for outputs off the 64-byte grid); the
+    output is complex64 [K][N_s], or float32 for power and R2R, inside NaN
+    guard bands, starting y_offset elements past a 64-byte aligned address.
+    Returns (y, y_guard_ok)."""
     real = bool(post & 4)
     cdt = np.float32 if real else np.complex64
     h = np.ascontiguousarray(h, dtype=cdt)
@@ -123,13 +128,22 @@ def forward_post(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int
     # the signal sits between NaN bands: a read outside [0, N_s) poisons the output
     sbuf = np.full(Ns + 2 * guard, np.nan, dtype=cdt)
     sbuf[guard:guard + Ns] = s
-    ybuf = np.full(K * Ns + 2 * guard, np.nan, dtype=dt)
+    raw = np.full(K * Ns + 2 * guard + 64, np.nan, dtype=dt)
+    lo = (-(raw.ctypes.data // esz)) % (64 // esz) + guard + y_offset  # aligned to 64 bytes, then y_offset
+    ybuf = raw[lo - guard:lo + K * Ns + guard]
     rc = emu().ols_emu_forward_post(N, ctypes.c_void_p(sbuf.ctypes.data + guard * sbuf.itemsize), Ns, _ptr(h), K, M,
                                     D, H, grid, int(post), ctypes.c_void_p(ybuf.ctypes.data + guard * esz))
     if rc != 0:
         raise RuntimeError(f"emulator returned {rc}")
     ok = bool(np.all(np.isnan(ybuf[:guard])) and np.all(np.isnan(ybuf[guard + K * Ns:])))
     return ybuf[guard:guard + K * Ns].reshape(K, Ns).copy(), ok
+
+
+def row_shift_geometry(y_addr: int, Ns: int, N: int, D: int, H: int, el: int) -> dict:
+    """The single-signal forward's hop and row-shift mask for a call."""
+    out = (ctypes.c_int32 * 2)()
+    emu().ols_emu_row_shift_geometry(ctypes.c_void_p(y_addr), Ns, N, D, H, el, out)
+    return {"H": out[0], "mask": out[1]}
 
 
 def stencil_delay(N: int, Meff: int, left: int, right: int) -> int:
@@ -193,11 +207,11 @@ def batch_geometry(N: int, M: int, y_addr: int, Ns: int) -> dict:
     kernel's rule)."""
     out = (ctypes.c_int32 * 3)()
     emu().ols_emu_batch_geometry(N, M, ctypes.c_void_p(y_addr), Ns, out)
-    return {"D": out[0], "H": out[1], "shifted": bool(out[2])}
+    return {"D": out[0], "H": out[1], "mask": out[2]}
 
 
-def row_shift(y_addr: int, Ns: int, D: int, r: int) -> int:
-    return int(emu().ols_emu_row_shift(ctypes.c_void_p(y_addr), Ns, D, r))
+def row_shift(y_addr: int, Ns: int, D: int, r: int, mask: int) -> int:
+    return int(emu().ols_emu_row_shift(ctypes.c_void_p(y_addr), Ns, D, r, mask))
 
 
 def batched(items, grid: int):

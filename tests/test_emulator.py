@@ -395,28 +395,28 @@ def test_stencil_delay_rule():
 
 
 def test_batched_row_shift_geometry():
-    """Rows off the 64-byte grid: the setup's rule delays filter r by
-    row_shift samples, which puts the first output of every store run (circular
-    positions on the 8-sample grid) on a granule boundary, for every row and
-    segment; aligned rows keep the plain geometry."""
+    """Rows off the 128-byte grid: the setup's rule delays filter r by
+    row_shift samples, which puts the first output of every store run
+    (circular positions on the 16-sample grid) on a line boundary, for every
+    row and segment; aligned rows keep the plain geometry."""
     for N, M in ((256, 40), (1024, 100), (2048, 513), (4096, 300)):
-        for Ns in (8000, 8001, 8003, 8007):
-            for y_off in (0, 1, 3, 7):
+        for Ns in (8000, 8001, 8003, 8008, 8015):
+            for y_off in (0, 1, 3, 8, 15):
                 y_addr = 1 << 20 | (y_off * 8)
                 geo = emu.batch_geometry(N, M, y_addr, Ns)
                 D, H = geo["D"], geo["H"]
-                aligned = y_off == 0 and Ns % 8 == 0
-                assert geo["shifted"] == (not aligned)
+                aligned = y_off == 0 and Ns % 16 == 0
+                assert geo["mask"] == (0 if aligned else 15)
                 if aligned:
                     assert H == N - D
                     continue
-                assert H % 8 == 0 and D + 7 + H <= N and H >= N - D - 15
+                assert H % 16 == 0 and D + 15 + H <= N and H >= N - D - 31
                 for r in range(5):
-                    dr = emu.row_shift(y_addr, Ns, D, r)
-                    assert 0 <= dr <= 7
+                    dr = emu.row_shift(y_addr, Ns, D, r, 15)
+                    assert 0 <= dr <= 15
                     for j in (0, 1, 5):
                         first = j * H - D + 0 - dr  # output at circular position 0 of segment j
-                        assert (y_addr // 8 + r * Ns + first) % 8 == 0, (N, M, Ns, y_off, r, j)
+                        assert (y_addr // 8 + r * Ns + first) % 16 == 0, (N, M, Ns, y_off, r, j)
 
 
 def test_batched_row_shift_vs_oracle():
@@ -433,3 +433,65 @@ def test_batched_row_shift_vs_oracle():
         for it, y in zip(items, outs):
             assert not np.isnan(y).any()
             assert np.all(_rel(y, conv.direct_conv(it["s"], it["h"])) <= 1e-5)
+
+
+SHIFT_CASES = [
+    # (Ns, K, M, N, flags, y_offset): flags 1 derivative, 2 power, 4 R2R
+    (5001, 3, 40, 256, 0, 1),
+    (5000, 3, 40, 256, 0, 3),
+    (20001, 4, 100, 1024, 1, 0),
+    (20003, 3, 300, 2048, 0, 7),
+    (20003, 2, 300, 2048, 2, 5),      # float rows: 16 outputs per granule
+    (30001, 2, 1000, 4096, 4, 9),     # R2R pairs
+    (30000, 2, 1000, 4096, 4 | 2, 0),
+    (40001, 2, 700, 8192, 1 | 2, 11),
+    (9, 2, 5, 512, 0, 2),
+]
+
+
+@pytest.mark.parametrize("Ns,K,M,N,flags,off", SHIFT_CASES)
+def test_forward_row_shift_vs_oracle(Ns, K, M, N, flags, off):
+    """Output rows off the 64-byte grid through the library's rule (filters
+    delayed per row, kept windows moved with them, hop with room for the
+    delay) give eq. (1) and its post-processing."""
+    real = bool(flags & 4)
+    mk = workloads.make_real_signal_filters if real else workloads.make_signal_filters
+    s, h = mk(Ns, K, M, seed=Ns + off)
+    Meff = M + 1 if flags & 1 else M
+    D = default_delay(N, Meff)
+    y, ok = emu.forward_post(s, h, N, D, N - D, grid=7, post=flags | 8, y_offset=off)
+    assert ok and not np.isnan(y).any()
+    ref = conv.direct_conv_real(s, h) if real else conv.direct_conv(s, h)
+    if flags & 1:
+        ref = post.derivative(ref)
+        ref = ref.real if real else ref
+    if flags & 2:
+        ref = ref * ref if real else post.power(ref)
+    assert np.all(_rel(y, ref) <= 1e-5), _rel(y, ref)
+
+
+def test_forward_row_shift_geometry():
+    """The rule for a call: rows on the 128-byte grid run unchanged; rows off
+    it get the mask of their line and a hop on the line grid with room for the
+    largest delay; every store run of every row then starts on a line."""
+    for el, LS in ((8, 16), (4, 32)):
+        for N, D in ((256, 48), (2048, 256), (4096, 1024), (8192, 704), (1024, 1001)):
+            H0 = N - D
+            for Ns in (1 << 20, (1 << 20) + 1, (1 << 20) + 8, (1 << 20) + 16, (1 << 20) + 31):
+                for off in (0, 1, 5, LS - 1):
+                    y_addr = (1 << 24) + off * el
+                    g = emu.row_shift_geometry(y_addr, Ns, N, D, H0, el)
+                    on_grid = off == 0 and Ns % LS == 0
+                    if on_grid:
+                        assert g == {"H": H0, "mask": 0}
+                        continue
+                    H, mask = g["H"], g["mask"]
+                    if mask == 0:  # no room for the delay: left as is
+                        assert H == H0 and N - D - (LS - 1) < LS
+                        continue
+                    assert mask == LS - 1 and H % LS == 0 and D + LS - 1 + H <= N and H > H0 - 2 * LS
+                    for r in range(4):
+                        d = (y_addr // el + r * Ns - D) % LS
+                        for j in (0, 1, 7):
+                            assert (y_addr // el + r * Ns + j * H - D - d) % LS == 0
+    assert emu.row_shift_geometry((1 << 24) + 8, 1001, 256, 248, 8, 8) == {"H": 8, "mask": 0}

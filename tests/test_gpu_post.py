@@ -163,3 +163,32 @@ def test_spectra_of_derivative_and_real_plans(ols):
     want = conv.fft(np.concatenate([hr.astype(np.float64), np.zeros((K, N - M))], axis=1)) / N
     assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
     plan.close()
+
+
+@pytest.mark.parametrize("Ns,K,M,N,real,phase", [
+    (20001, 3, 256, 2048, False, 1), (20003, 2, 300, 1024, False, 11), (30000, 3, 1000, 4096, False, 5),
+    (9999, 4, 40, 256, True, 3), (20001, 3, 256, 2048, True, 15), (40001, 2, 2000, 8192, True, 7)])
+def test_float_rows_off_grid_full(ols, Ns, K, M, N, real, phase):
+    """float32 output rows (the power, R2R) that start off the 64-byte grid
+    (16 outputs per granule): y starts `phase` floats past a granule boundary
+    of a NaN-filled buffer; every output and both guard bands are checked."""
+    say(f"float rows phase {phase}: Ns={Ns} K={K} M={M} N={N} real={real}")
+    if real:
+        s, h = workloads.make_real_signal_filters(Ns, K, M, seed=Ns + phase)
+        plan = ols.OLSPlan(dev(h), N=N)
+        ref = conv.direct_conv_real(s, h)
+    else:
+        s, h = workloads.make_signal_filters(Ns, K, M, seed=Ns + phase)
+        plan = ols.OLSPlan(dev(h), N=N, power=True)
+        ref = post.power(conv.direct_conv(s, h))
+    buf = torch.full((K * Ns + 2 * GUARD,), float("nan"), dtype=torch.float32, device="cuda")
+    assert buf.data_ptr() % 64 == 0
+    y = buf[GUARD + phase:GUARD + phase + K * Ns].view(K, Ns)
+    plan.forward(dev(s), y)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(buf[:GUARD + phase]).all()), "guard before y written"
+    assert bool(torch.isnan(buf[GUARD + phase + K * Ns:]).all()), "guard after y written"
+    got = y.cpu().numpy()
+    assert not np.isnan(got).any(), "output not written everywhere"
+    assert np.all(rel_rows(got, ref) <= TOL), rel_rows(got, ref)
+    plan.close()
