@@ -22,10 +22,11 @@
  *     thread's most recent failure;
  *   - index arithmetic is 64-bit (K * N_s may exceed 2^31);
  *   - a plan holds mutable device state -- its filter spectra (rewritten by
- *     ols_plan_update_filters) and its backward workspace (rewritten by every
- *     ols_backward) -- so the calls that use one plan must be ordered: enqueue
- *     them on one stream, or order the streams with events.  Two plans never
- *     share state.
+ *     ols_plan_update_filters), their per-row delayed copy (rewritten by an
+ *     ols_forward whose output rows are off the 128-byte grid) and its
+ *     backward workspace (rewritten by every ols_backward) -- so the calls
+ *     that use one plan must be ordered: enqueue them on one stream, or order
+ *     the streams with events.  Two plans never share state.
  */
 #ifndef OLS_H_
 #define OLS_H_
@@ -72,9 +73,10 @@ typedef enum {
  *          used on any stream once this work is complete (the call itself
  *          synchronises `stream` before returning, so it is)
  *
- * The plan owns device memory for the K filter spectra (8*K*N bytes) and the
- * twiddle tables, all allocated here; forward calls allocate nothing.  `h`
- * may be freed as soon as the call returns.
+ * The plan owns device memory for the K filter spectra and their per-row
+ * delayed copy (2 * 8*K*N bytes) and the twiddle tables, all allocated here;
+ * forward calls allocate nothing.  `h` may be freed as soon as the call
+ * returns.
  * Errors: INVALID_VALUE (null plan/h, K < 1, M < 1, M > N), UNSUPPORTED (N),
  * OUT_OF_MEMORY, HIP.
  */
@@ -200,10 +202,13 @@ ols_status_t ols_plan_get_spectra(ols_plan_t plan, void* out, ols_stream_t strea
  *        as the plan's flags say; must not overlap s (out of place only)
  * Errors: INVALID_VALUE (null plan/s/y, N_s < 0, misaligned, overlap,
  * K*N_s*8 overflow), HIP (launch failure).  Allocates nothing.
- * Speed: rows that start on a 64-byte boundary (y 64-byte aligned and N_s a
- * multiple of 8, of 16 for float32 outputs) stream straight to HBM; other
- * rows take the default cache policy for their partial 64-byte granules and
- * run up to ~1.2x slower.
+ * Rows off the 128-byte grid (y not 128-byte aligned, or N_s not a multiple
+ * of 16, of 32 for float32 outputs): the call first writes the plan's
+ * delayed spectra (filter r delayed by 0..15 (31) samples, as the spectrum
+ * times the delay's phase) on `stream`, and runs with the hop rounded down to
+ * a multiple of 16 (32) with room for the delay, so that every store
+ * instruction starts on a 128-byte line; results agree with an aligned call
+ * to rounding.  Such rows then run within ~5 % of aligned ones.
  */
 ols_status_t ols_forward(ols_plan_t plan, const void* s, int64_t N_s, void* y, ols_stream_t stream);
 
@@ -311,7 +316,10 @@ ols_status_t ols_batched_workspace_size(const ols_batch_item_t* host_items, int3
  *      checks, chooses each N, orders the items by (N, filters per unit) and
  *      lays out the tile list and the spectra in the workspace;
  *   2. the filter spectra of every item, FFT_N(pad h)/N, into the workspace
- *      (so a replay sees the filters' current values);
+ *      (so a replay sees the filters' current values); an item whose output
+ *      rows are off the 128-byte grid gets each filter delayed by its row's
+ *      line phase (0..15 samples) and a hop with room for it, as ols_forward
+ *      does;
  *   3. one persistent forward kernel over the segment tiles of all items.
  * Every replay reads dev_items again: the caller may change the items (new
  * pointers, new filters, other shapes that fit the workspace) between calls.

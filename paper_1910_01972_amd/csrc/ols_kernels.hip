@@ -1262,7 +1262,7 @@ struct ols_plan_s {
   void* bwd_mem = nullptr;  // the adjoint's scratch, allocated by ols_plan_reserve_backward
   BwdWorkspace bwd{};       // carved from bwd_mem for the adjoint's full grid
   float2* spectra = nullptr;
-  float2* spectra_delayed = nullptr;  // per-row delayed copy for output rows off the 64-byte grid
+  float2* spectra_delayed = nullptr;  // per-row delayed copy for output rows off the 128-byte grid
   float2* twiddles = nullptr;
 };
 
@@ -1364,6 +1364,8 @@ struct Kern {
     const RowShift rs = row_shift_geometry(y, Ns, N, p->D, p->H, float_out ? 4 : 8, !p->stencil_on);
     const float2* F = p->spectra;
     if (rs.mask) {
+      // rewritten by every such call (a few microseconds): the spectra may
+      // have changed since, also by a graph replay the host does not see
       const hipError_t e = delayed(p->spectra, p->K, p->spectra_delayed,
                                    SpectraShift{y, Ns, float_out ? 4 : 8, p->D, rs.mask}, st);
       if (e != hipSuccess) return e;
