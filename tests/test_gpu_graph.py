@@ -104,3 +104,39 @@ def test_backward_graph_replays(ols):
         assert torch.equal(a, ds) and torch.equal(b, dh)
     plan.close()
     sys.stdout.flush()
+
+
+@pytest.mark.parametrize("kind", ["plain", "power", "real"])
+def test_forward_graph_replays_rows_off_grid(ols, kind):
+    """Rows off the 128-byte grid: the captured call carries its own
+    delayed-spectra kernel, so replays stay right when, between them, the
+    filters change and an eager call with other row phases rewrites the
+    plan's delayed spectra."""
+    print(f"graph forward off-grid {kind}", flush=True)
+    Ns, K, M, N = 40001, 4, 200, 1024
+    real = kind == "real"
+    gen = workloads.make_real_signal_filters if real else workloads.make_signal_filters
+    s, h = gen(Ns, K, M, seed=72)
+    plan = ols.OLSPlan(dev(h), N=N, power=kind == "power")
+    sd = dev(s)
+    dt = torch.float32 if kind != "plain" else torch.complex64
+    y = torch.empty((K, Ns), dtype=dt, device="cuda")
+    other = torch.empty((K * (Ns - 2) + 3,), dtype=dt, device="cuda")
+    y_other = other[3:].view(K, Ns - 2)  # another length and row phase
+    graph = capture(lambda st: plan.forward(sd, y=y, stream=st))
+    for rep in range(3):
+        _, h2 = gen(1, K, M, seed=700 + rep)
+        hd = dev(h2)
+        plan.update_filters(hd)
+        plan.forward(sd[:Ns - 2], y=y_other)  # eager, other phases
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        if real:
+            ref = conv.direct_conv_real(s, h2)
+        else:
+            ref = conv.direct_conv(s, h2)
+            if kind == "power":
+                ref = post.power(ref)
+        assert np.all(rel_rows(y.cpu().numpy(), ref) <= TOL), rep
+    plan.close()
