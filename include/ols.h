@@ -203,7 +203,8 @@ ols_status_t ols_plan_get_spectra(ols_plan_t plan, void* out, ols_stream_t strea
  * Errors: INVALID_VALUE (null plan/s/y, N_s < 0, misaligned, overlap,
  * K*N_s*8 overflow), HIP (launch failure).  Allocates nothing.
  * Rows off the 128-byte grid (y not 128-byte aligned, or N_s not a multiple
- * of 16, of 32 for float32 outputs): the call first writes the plan's
+ * of 16, of 32 for float32 outputs), in calls of K*N_s >= 2^22 outputs on
+ * plans without a stencil: the call first writes the plan's
  * delayed spectra (filter r delayed by 0..15 (31) samples, as the spectrum
  * times the delay's phase) on `stream`, and runs with the hop rounded down to
  * a multiple of 16 (32) with room for the delay, so that every store

@@ -228,8 +228,9 @@ void forward_range(const float2* s, int64_t Ns, const float2* F, float2* y, int 
   }
 }
 
-// post & 8: the library's treatment of output rows off the 64-byte grid
-// (row_shift_geometry on the given D and H; delayed filters).
+// post & 8: the library's treatment of output rows off the 128-byte grid
+// (row_shift_geometry on the given D and H; delayed filters), whatever the
+// size (the library applies it from 2^22 outputs per call on).
 template <int N>
 int forward(const float2* s, int64_t Ns, const float2* h, int K, int M, int D, int H, int grid, float2* y,
             int post = 0, const Stencil* st = nullptr) {

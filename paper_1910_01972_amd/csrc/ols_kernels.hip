@@ -1207,6 +1207,12 @@ __global__ void ols_copy_kernel(float4* __restrict__ dst, const float4* __restri
 // ===========================================================================
 using namespace ols;
 
+// A single-signal call re-aligns its output rows (row_shift_geometry) only
+// from this many outputs (K * N_s) on: below it the delayed-spectra kernel it
+// launches first costs more than the aligned stores save (measured 1.5-2.5 us
+// extra per call at 2^16-2^20 outputs, 2-3 % saved at 2^22-2^23, 14 % at 2^28).
+constexpr int64_t SHIFT_MIN_OUTPUTS = (int64_t)1 << 22;
+
 // Scratch of the adjoint: partial ds windows of tiles split between
 // workgroups, per-workgroup dh lag partials and their chunk sums.  Sized for a
 // grid of persistent workgroups (bwd_ws_bytes); every part is written before
@@ -1361,7 +1367,8 @@ struct Kern {
     // output rows off the 64-byte grid run with per-row delayed filters (the
     // delayed copy is rewritten on the call's stream before the forward)
     const bool float_out = (p->flags & (OLS_REAL | OLS_POST_POWER)) != 0;
-    const RowShift rs = row_shift_geometry(y, Ns, N, p->D, p->H, float_out ? 4 : 8, !p->stencil_on);
+    const RowShift rs = row_shift_geometry(y, Ns, N, p->D, p->H, float_out ? 4 : 8,
+                                           !p->stencil_on && (int64_t)p->K * Ns >= SHIFT_MIN_OUTPUTS);
     const float2* F = p->spectra;
     if (rs.mask) {
       // rewritten by every such call (a few microseconds): the spectra may

@@ -113,7 +113,7 @@ def test_forward_graph_replays_rows_off_grid(ols, kind):
     filters change and an eager call with other row phases rewrites the
     plan's delayed spectra."""
     print(f"graph forward off-grid {kind}", flush=True)
-    Ns, K, M, N = 40001, 4, 200, 1024
+    Ns, K, M, N = (1 << 20) + 1, 4, 64, 1024  # >= 2^22 outputs: the call re-aligns its rows
     real = kind == "real"
     gen = workloads.make_real_signal_filters if real else workloads.make_signal_filters
     s, h = gen(Ns, K, M, seed=72)

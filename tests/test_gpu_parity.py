@@ -276,7 +276,9 @@ def test_filter_bank_off_grid_rows_sampled(ols, extra):
 
 
 ROW_PHASE_CASES = [
-    # (Ns, K, M, N, derivative)
+    # (Ns, K, M, N, derivative); from 2^22 outputs on, rows are re-aligned per row
+    ((1 << 20) + 1, 4, 64, 1024, False),
+    ((1 << 20) + 5, 4, 300, 2048, True),
     (20001, 3, 256, 2048, False),
     (20003, 3, 250, 2048, False),
     (9999, 5, 40, 256, False),      # transforms narrower than a wave (per-lane stores)

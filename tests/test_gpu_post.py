@@ -167,7 +167,10 @@ def test_spectra_of_derivative_and_real_plans(ols):
 
 @pytest.mark.parametrize("Ns,K,M,N,real,phase", [
     (20001, 3, 256, 2048, False, 1), (20003, 2, 300, 1024, False, 11), (30000, 3, 1000, 4096, False, 5),
-    (9999, 4, 40, 256, True, 3), (20001, 3, 256, 2048, True, 15), (40001, 2, 2000, 8192, True, 7)])
+    (9999, 4, 40, 256, True, 3), (20001, 3, 256, 2048, True, 15), (40001, 2, 2000, 8192, True, 7),
+    # >= 2^22 outputs: rows re-aligned to 128-byte lines (filters delayed per row)
+    ((1 << 20) + 1, 4, 64, 1024, False, 0), ((1 << 20) + 16, 4, 64, 2048, True, 5),
+    ((1 << 20) + 3, 4, 300, 4096, False, 9)])
 def test_float_rows_off_grid_full(ols, Ns, K, M, N, real, phase):
     """float32 output rows (the power, R2R) that start off the 64-byte grid
     (16 outputs per granule): y starts `phase` floats past a granule boundary
