@@ -709,12 +709,15 @@ struct RowShift {
 };
 constexpr int SHIFT_LINE = 128;  // bytes
 // H: the plan's hop; el: bytes per output; allowed: the kernel supports it.
+// The hop the call runs with is H rounded down to a multiple of LS, and no
+// more than the room the delay leaves (N - D - (LS - 1), rounded down too);
+// below LS the rows stay as they are.
 OLS_HD RowShift row_shift_geometry(const void* y, int64_t Ns, int N, int D, int H, int el, bool allowed) {
   const int LS = SHIFT_LINE / el;
   const bool off = ((uintptr_t)y & (SHIFT_LINE - 1)) != 0 || (Ns & (LS - 1)) != 0;
   if (!allowed || !off) return RowShift{H, 0};
-  if ((H & (LS - 1)) == 0 && D + (LS - 1) + H <= N) return RowShift{H, LS - 1};
-  const int hs = (N - D - (LS - 1)) & ~(LS - 1);
+  const int room = (N - D - (LS - 1)) & ~(LS - 1);
+  const int hs = (H & ~(LS - 1)) < room ? (H & ~(LS - 1)) : room;
   return hs >= LS ? RowShift{hs, LS - 1} : RowShift{H, 0};
 }
 // Delay of row r (0 .. mask): output n of row r is element r*N_s + n of y

@@ -379,3 +379,21 @@ def test_signal_longer_than_2p31_sampled(ols):
     rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
     assert np.all(rel <= TOL), rel
     plan.close()
+
+
+@pytest.mark.parametrize("hop", [900, 500, 100])
+def test_row_realignment_with_chosen_hop(ols, hop):
+    """A plan with a chosen hop and output rows off the 128-byte grid, large
+    enough (>= 2^22 outputs) to be re-aligned: the call runs with the hop
+    rounded down to the line grid, and every output matches eq. (1)."""
+    Ns, K, M, N = (1 << 20) + 7, 4, 64, 1024
+    say(f"row re-alignment, hop {hop}")
+    s, h = workloads.make_signal_filters(Ns, K, M, seed=hop)
+    plan = ols.OLSPlan(dev(h), N=N)
+    plan.set_hop(hop)
+    buf, y = guarded_output(K, Ns)
+    plan.forward(dev(s), y)
+    torch.cuda.synchronize()
+    check_guards(buf, K, Ns)
+    assert np.all(rel_rows(y.cpu().numpy(), conv.direct_conv(s, h)) <= TOL)
+    plan.close()
