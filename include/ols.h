@@ -21,12 +21,12 @@
  *     call enqueues nothing; ols_last_error() gives a message for the calling
  *     thread's most recent failure;
  *   - index arithmetic is 64-bit (K * N_s may exceed 2^31);
- *   - a plan holds mutable device state -- its filter spectra (rewritten by
- *     ols_plan_update_filters), their per-row delayed copy (rewritten by an
- *     ols_forward whose output rows are off the 128-byte grid) and its
- *     backward workspace (rewritten by every ols_backward) -- so the calls
- *     that use one plan must be ordered: enqueue them on one stream, or order
- *     the streams with events.  Two plans never share state.
+ *   - ols_forward only reads its plan, so forward calls of one plan may run
+ *     on several streams at once; a plan's other device state -- its filter
+ *     spectra (rewritten by ols_plan_update_filters) and its backward
+ *     workspace (rewritten by every ols_backward) -- makes those calls
+ *     ordered with the calls that read it: enqueue them on one stream, or
+ *     order the streams with events.  Two plans never share state.
  */
 #ifndef OLS_H_
 #define OLS_H_
@@ -73,10 +73,11 @@ typedef enum {
  *          used on any stream once this work is complete (the call itself
  *          synchronises `stream` before returning, so it is)
  *
- * The plan owns device memory for the K filter spectra and their per-row
- * delayed copy (2 * 8*K*N bytes) and the twiddle tables, all allocated here;
- * forward calls allocate nothing.  `h` may be freed as soon as the call
- * returns.
+ * The plan owns device memory for the K filter spectra (8*K*N bytes), the
+ * same spectra delayed by 0 .. LS-1 samples (LS = 16, or 32 for float32
+ * outputs: 8*K*N*LS bytes, allocated only when that is at most 256 MiB; see
+ * ols_forward) and the twiddle tables, all allocated here; forward calls
+ * allocate nothing.  `h` may be freed as soon as the call returns.
  * Errors: INVALID_VALUE (null plan/h, K < 1, M < 1, M > N), UNSUPPORTED (N),
  * OUT_OF_MEMORY, HIP.
  */
@@ -203,13 +204,13 @@ ols_status_t ols_plan_get_spectra(ols_plan_t plan, void* out, ols_stream_t strea
  * Errors: INVALID_VALUE (null plan/s/y, N_s < 0, misaligned, overlap,
  * K*N_s*8 overflow), HIP (launch failure).  Allocates nothing.
  * Rows off the 128-byte grid (y not 128-byte aligned, or N_s not a multiple
- * of 16, of 32 for float32 outputs), in calls of K*N_s >= 2^22 outputs on
- * plans without a stencil: the call first writes the plan's
- * delayed spectra (filter r delayed by 0..15 (31) samples, as the spectrum
- * times the delay's phase) on `stream`, and runs with the hop rounded down to
- * a multiple of 16 (32) with room for the delay, so that every store
- * instruction starts on a 128-byte line; results agree with an aligned call
- * to rounding.  Such rows then run within ~5 % of aligned ones.
+ * of LS = 16, of 32 for float32 outputs), in calls of K*N_s >= 2^22 outputs
+ * on plans that hold their delayed spectra and have no stencil: filter r is
+ * taken delayed by 0..LS-1 samples (the plan's precomputed spectrum times
+ * the delay's phase) so that every store instruction of row r starts on a
+ * 128-byte line, and the call runs with the hop rounded down to a multiple of
+ * LS with room for the delay; results agree with an aligned call to
+ * rounding.  Such rows then run within ~5 % of aligned ones.
  */
 ols_status_t ols_forward(ols_plan_t plan, const void* s, int64_t N_s, void* y, ols_stream_t stream);
 

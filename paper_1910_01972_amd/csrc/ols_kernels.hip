@@ -184,25 +184,26 @@ __global__ void ols_spectra_natural_kernel(const float2* __restrict__ F, int K, 
   out[(int64_t)r * N + spectrum_index<N>(g, reg)] = F[i];
 }
 
-// Filter spectra delayed per row, for output rows off the 64-byte grid:
-// out[r] = F[r] * exp(-2 pi i k d_r / N), the spectrum of filter r delayed by
-// d_r = row_delay(sh.y, sh.el, sh.Ns, sh.D, r, sh.mask) samples, in the same
-// storage order (the phase from the exact integer k * d_r mod N, in float64).
+// The filter spectra delayed by every d = 0 .. LS-1 samples, for output rows
+// off the 128-byte grid: out[d][r] = F[r] * exp(-2 pi i k d / N), in the same
+// storage order (the phase from the exact integer k * d mod N, in float64).
+// Computed with the spectra, so that a forward call only reads the plan.
 template <int N>
-__global__ void ols_spectra_delay_kernel(const float2* __restrict__ F, int K, float2* __restrict__ out,
-                                         const SpectraShift sh) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // over K * N
-  if (i >= (int64_t)K * N) return;
-  const int r = (int)(i / N);
-  const int rem = (int)(i - (int64_t)r * N);  // = spectrum_offset(reg, g)
+__global__ void ols_spectra_delays_kernel(const float2* __restrict__ F, int K, int LS, float2* __restrict__ out) {
+  const int64_t KN = (int64_t)K * N;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // over LS * K * N
+  if (i >= KN * LS) return;
+  const int d = (int)(i / KN);
+  const int64_t ir = i - d * KN;  // element of F
+  const int r = (int)(ir / N);
+  const int rem = (int)(ir - (int64_t)r * N);  // = spectrum_offset(reg, g)
   const int pair = rem >> 1, j = pair / Geo<N>::G, g = pair - j * Geo<N>::G;
   const int reg = 2 * j + (rem & 1);
   const int k = spectrum_index<N>(g, reg);
-  const int d = row_delay(sh.y, sh.el, sh.Ns, sh.D, r, sh.mask);
   const int m = (int)(((int64_t)k * d) % N);
   double sn, cs;
   sincospi(2.0 * (double)m / (double)N, &sn, &cs);
-  out[i] = cmul(F[i], make_float2((float)cs, (float)(-sn)));
+  out[i] = cmul(F[ir], make_float2((float)cs, (float)(-sn)));
 }
 
 // ---------------------------------------------------------------------------
@@ -245,15 +246,19 @@ constexpr int forward_lds() {
 
 // STAGE: the outputs go through the non-local stencil stage (st) instead of
 // the plain store; the output rows then hold st->J * N_s elements.
-// shift_mask != 0: filter r's spectrum carries a delay of
-// row_delay(yv, el, Ns, D, r, shift_mask) samples (output rows off the
-// 64-byte grid), and row r's kept positions start that much later.
+// shift_mask != 0 (output rows off the 128-byte grid): row r's filter is
+// delayed by d_r = row_delay(yv, el, Ns, D, r, shift_mask) samples, and row
+// r's kept positions start d_r later.  Its spectrum is row
+// r + delay_rows * d_r of F: the plan keeps the spectra for every delay
+// (delay_rows = K), a batched item has its rows' delayed spectra computed in
+// place (delay_rows = 0).
 template <int N, int NF, bool POWER = false, bool REAL = false, int SMODE = STORE_NT_WHOLE,
           bool PF = prefetch_spectra<N, NF>(), bool STAGE = false>
 __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64_t Ns, const float2* __restrict__ F,
                                               void* __restrict__ yv, int K, int D, int H,
                                               const float2 (&tw)[Geo<N>::TWR], int64_t u0, int64_t u1, float2* lds,
-                                              int& par, const Stencil* st = nullptr, int shift_mask = 0) {
+                                              int& par, const Stencil* st = nullptr, int shift_mask = 0,
+                                              int delay_rows = 0) {
   using GE = Geo<N>;
   const int tid = threadIdx.x;
   const int grp = tid / GE::G, g = tid - grp * GE::G;
@@ -286,11 +291,13 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
   };
   // spectra of filter group q; filters past K (a ragged last group) reuse the
   // last filter's spectrum and are not stored
+  constexpr int EL = (REAL || POWER) ? 4 : 8;  // bytes per output sample
   auto load_group = [&](float2 (&x)[NF][16], int q) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const int r = q * NF + f;
-      load_spectrum<N>(x[f], Fg, r < K ? r : K - 1, g);
+      const int rr = r < K ? r : K - 1;
+      load_spectrum<N>(x[f], Fg, rr + delay_rows * row_delay(yv, EL, Ns, D, rr, shift_mask), g);
     }
   };
   // stencil phases of filter r's segment (pair) sg, staged at region
@@ -337,7 +344,6 @@ __device__ __forceinline__ void forward_units(const void* __restrict__ sv, int64
       }
     }
   };
-  constexpr int EL = (REAL || POWER) ? 4 : 8;  // bytes per output sample
   auto store_group = [&](const float2 (&x)[NF][16], int q, int64_t sg) {
     if constexpr (STAGE) {
       stage_group(x, q, sg);
@@ -405,8 +411,8 @@ __device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64
   float2 tw[Geo<N>::TWR];
   load_lane_twiddles<N>(tw, twt, threadIdx.x % Geo<N>::G);
   // the stage's accumulators take the registers of the spectrum prefetch
-  forward_units<N, NF, POWER, REAL, SMODE, prefetch_spectra<N, NF>() && !STAGE, STAGE>(sv, Ns, F, yv, K, D, H, tw, u0,
-                                                                                        u1, lds, par, st, shift_mask);
+  forward_units<N, NF, POWER, REAL, SMODE, prefetch_spectra<N, NF>() && !STAGE, STAGE>(
+      sv, Ns, F, yv, K, D, H, tw, u0, u1, lds, par, st, shift_mask, K);
 }
 
 // shift_mask: 0, or the row shift of output rows off the 64-byte grid
@@ -1244,10 +1250,15 @@ __global__ void ols_copy_kernel(float4* __restrict__ dst, const float4* __restri
 using namespace ols;
 
 // A single-signal call re-aligns its output rows (row_shift_geometry) only
-// from this many outputs (K * N_s) on: below it the delayed-spectra kernel it
-// launches first costs more than the aligned stores save (measured 1.5-2.5 us
-// extra per call at 2^16-2^20 outputs, 2-3 % saved at 2^22-2^23, 14 % at 2^28).
+// from this many outputs (K * N_s) on: smaller calls are bound by launch and
+// memory latency, where aligned stores measured no gain, while re-aligned
+// rows run with a hop up to two lines shorter (3-8 % saved at 2^22-2^23
+// outputs, 14 % at 2^28).
 constexpr int64_t SHIFT_MIN_OUTPUTS = (int64_t)1 << 22;
+// Device memory a plan may spend on the spectra for every row delay (16
+// copies of its spectra for complex outputs, 32 for float32 ones); larger
+// plans do not re-align their rows.
+constexpr int64_t SHIFT_SPECTRA_MAX_BYTES = (int64_t)256 << 20;
 
 // Scratch of the adjoint: partial ds windows of tiles split between
 // workgroups, per-workgroup dh lag partials and their chunk sums.  Sized for a
@@ -1304,7 +1315,8 @@ struct ols_plan_s {
   void* bwd_mem = nullptr;  // the adjoint's scratch, allocated by ols_plan_reserve_backward
   BwdWorkspace bwd{};       // carved from bwd_mem for the adjoint's full grid
   float2* spectra = nullptr;
-  float2* spectra_delayed = nullptr;  // per-row delayed copy for output rows off the 128-byte grid
+  float2* spectra_delays = nullptr;  // [delay_ls][K][N]: the spectra delayed by 0 .. delay_ls-1 samples
+  int delay_ls = 0;                   // outputs per 128-byte line (0: no delayed spectra, rows not re-aligned)
   float2* twiddles = nullptr;
 };
 
@@ -1349,11 +1361,11 @@ struct Kern {
                        SpectraShift{});
     return hipGetLastError();
   }
-  static hipError_t delayed(const float2* F, int K, float2* out, const SpectraShift& sh, hipStream_t st) {
-    const int64_t total = (int64_t)K * N;
+  static hipError_t delays(const float2* F, int K, int LS, float2* out, hipStream_t st) {
+    const int64_t total = (int64_t)K * N * LS;
     const int threads = 256;
     const int64_t blocks = (total + threads - 1) / threads;
-    hipLaunchKernelGGL(ols_spectra_delay_kernel<N>, dim3((unsigned)blocks), dim3(threads), 0, st, F, K, out, sh);
+    hipLaunchKernelGGL(ols_spectra_delays_kernel<N>, dim3((unsigned)blocks), dim3(threads), 0, st, F, K, LS, out);
     return hipGetLastError();
   }
   static hipError_t natural(const float2* F, int K, float2* out, hipStream_t st) {
@@ -1402,18 +1414,13 @@ struct Kern {
   static hipError_t forward(const ols_plan_s* p, const void* s, int64_t Ns, void* y, hipStream_t st) {
     // output rows off the 64-byte grid run with per-row delayed filters (the
     // delayed copy is rewritten on the call's stream before the forward)
+    // output rows off the 128-byte grid read the plan's spectra for each
+    // row's delay (the call only reads the plan)
     const bool float_out = (p->flags & (OLS_REAL | OLS_POST_POWER)) != 0;
-    const RowShift rs = row_shift_geometry(y, Ns, N, p->D, p->H, float_out ? 4 : 8,
-                                           !p->stencil_on && (int64_t)p->K * Ns >= SHIFT_MIN_OUTPUTS);
-    const float2* F = p->spectra;
-    if (rs.mask) {
-      // rewritten by every such call (a few microseconds): the spectra may
-      // have changed since, also by a graph replay the host does not see
-      const hipError_t e = delayed(p->spectra, p->K, p->spectra_delayed,
-                                   SpectraShift{y, Ns, float_out ? 4 : 8, p->D, rs.mask}, st);
-      if (e != hipSuccess) return e;
-      F = p->spectra_delayed;
-    }
+    const RowShift rs = row_shift_geometry(
+        y, Ns, N, p->D, p->H, float_out ? 4 : 8,
+        p->spectra_delays && !p->stencil_on && (int64_t)p->K * Ns >= SHIFT_MIN_OUTPUTS);
+    const float2* F = rs.mask ? p->spectra_delays : p->spectra;
     const int H = rs.H;
     const int64_t nseg = (Ns + H - 1) / H;
     const int64_t ntrans = (p->flags & OLS_REAL) ? (nseg + 1) / 2 : nseg;  // R2R: segment pairs
@@ -1506,6 +1513,12 @@ template <int N>
 struct RunSpectra {
   static hipError_t run(const void* h, int K, int M, float2* F, const float2* tw, hipStream_t st, int diff, int real) {
     return Kern<N>::spectra(h, K, M, F, tw, st, diff, real);
+  }
+};
+template <int N>
+struct RunDelays {
+  static hipError_t run(const float2* F, int K, int LS, float2* out, hipStream_t st) {
+    return Kern<N>::delays(F, K, LS, out, st);
   }
 };
 template <int N>
@@ -1635,7 +1648,7 @@ void destroy_plan(ols_plan_s* p) {
   if (!p) return;
   if (p->bwd_mem) (void)hipFree(p->bwd_mem);
   if (p->spectra) (void)hipFree(p->spectra);
-  if (p->spectra_delayed) (void)hipFree(p->spectra_delayed);
+  if (p->spectra_delays) (void)hipFree(p->spectra_delays);
   if (p->twiddles) (void)hipFree(p->twiddles);
   delete p;
 }
@@ -1791,14 +1804,23 @@ ols_status_t ols_plan_ex(ols_plan_t* plan, const void* h, int32_t K, int32_t M, 
     if (e != hipSuccess) { destroy_plan(p); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "twiddle allocation"); }
     e = hipMalloc(&p->spectra, (size_t)K * N * sizeof(float2));
     if (e != hipSuccess) { destroy_plan(p); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "spectra allocation"); }
-    e = hipMalloc(&p->spectra_delayed, (size_t)K * N * sizeof(float2));
-    if (e != hipSuccess) { destroy_plan(p); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "spectra allocation"); }
+    // the spectra for every row delay, when they fit the budget
+    const int ls = (flags & (OLS_REAL | OLS_POST_POWER)) ? 32 : 16;
+    if ((int64_t)K * N * ls * (int64_t)sizeof(float2) <= SHIFT_SPECTRA_MAX_BYTES) {
+      e = hipMalloc(&p->spectra_delays, (size_t)K * N * ls * sizeof(float2));
+      if (e != hipSuccess) { destroy_plan(p); (void)hipGetLastError(); return fail(OLS_ERROR_OUT_OF_MEMORY, "spectra allocation"); }
+      p->delay_ls = ls;
+    }
     hipStream_t st = (hipStream_t)stream;
     e = hipMemcpyAsync(p->twiddles, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "twiddle upload"); }
     e = dispatch<RunSpectra>(N, h, K, M, p->spectra, (const float2*)p->twiddles, st,
                              (flags & OLS_POST_DERIVATIVE) ? 1 : 0, (flags & OLS_REAL) ? 1 : 0);
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "filter spectra launch"); }
+    if (p->spectra_delays) {
+      e = dispatch<RunDelays>(N, (const float2*)p->spectra, K, p->delay_ls, p->spectra_delays, st);
+      if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "delayed spectra launch"); }
+    }
     e = hipStreamSynchronize(st);  // the host twiddle buffer and h are released after this
     if (e != hipSuccess) { destroy_plan(p); return hip_fail(e, "plan synchronisation"); }
     *plan = p;
@@ -1817,6 +1839,11 @@ ols_status_t ols_plan_update_filters(ols_plan_t p, const void* h, ols_stream_t s
                                         (hipStream_t)stream, (p->flags & OLS_POST_DERIVATIVE) ? 1 : 0,
                                         (p->flags & OLS_REAL) ? 1 : 0);
     if (e != hipSuccess) return hip_fail(e, "filter spectra launch");
+    if (p->spectra_delays) {
+      e = dispatch<RunDelays>(p->N, (const float2*)p->spectra, p->K, p->delay_ls, p->spectra_delays,
+                              (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "delayed spectra launch");
+    }
     return OLS_SUCCESS;
   } catch (...) {
     return fail(OLS_ERROR_INTERNAL, "exception in ols_plan_update_filters");

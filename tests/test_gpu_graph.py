@@ -108,10 +108,9 @@ def test_backward_graph_replays(ols):
 
 @pytest.mark.parametrize("kind", ["plain", "power", "real"])
 def test_forward_graph_replays_rows_off_grid(ols, kind):
-    """Rows off the 128-byte grid: the captured call carries its own
-    delayed-spectra kernel, so replays stay right when, between them, the
-    filters change and an eager call with other row phases rewrites the
-    plan's delayed spectra."""
+    """Rows off the 128-byte grid (re-aligned, >= 2^22 outputs): replays read
+    the plan's delayed spectra, which an eager filter update rewrites, and
+    stay right when an eager call with other row phases runs in between."""
     print(f"graph forward off-grid {kind}", flush=True)
     Ns, K, M, N = (1 << 20) + 1, 4, 64, 1024  # >= 2^22 outputs: the call re-aligns its rows
     real = kind == "real"

@@ -397,3 +397,28 @@ def test_row_realignment_with_chosen_hop(ols, hop):
     check_guards(buf, K, Ns)
     assert np.all(rel_rows(y.cpu().numpy(), conv.direct_conv(s, h)) <= TOL)
     plan.close()
+
+
+def test_forward_concurrent_streams_rows_off_grid(ols):
+    """ols_forward only reads its plan: two calls of one plan with different
+    row phases (both re-aligned) run concurrently on two streams and both
+    match eq. (1)."""
+    K, M, N = 4, 64, 1024
+    NsA, NsB = (1 << 20) + 9, (1 << 20) + 3  # both >= 2^22 outputs with K = 4
+    s, h = workloads.make_signal_filters(NsA, K, M, seed=404)
+    plan = ols.OLSPlan(dev(h), N=N)
+    sd = dev(s)
+    bufA = torch.full((K * NsA + 16,), complex(float("nan"), float("nan")), dtype=torch.complex64, device="cuda")
+    bufB = torch.full((K * NsB + 16,), complex(float("nan"), float("nan")), dtype=torch.complex64, device="cuda")
+    yA = bufA[1:1 + K * NsA].view(K, NsA)
+    yB = bufB[3:3 + K * NsB].view(K, NsB)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        plan.forward(sd, y=yA, stream=s1)
+        plan.forward(sd[:NsB], y=yB, stream=s2)
+    torch.cuda.synchronize()
+    ref = conv.direct_conv(s, h)
+    assert np.all(rel_rows(yA.cpu().numpy(), ref) <= TOL)
+    assert np.all(rel_rows(yB.cpu().numpy(), ref[:, :NsB]) <= TOL)
+    plan.close()
