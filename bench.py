@@ -297,6 +297,24 @@ def roof_measurement(mib: int = 2048, launches: int = 20) -> dict:
             "fill_GBps": nbytes / (fill_ms * 1e-3) / 1e9}
 
 
+SIDE_SETTLE_S = 0.2  # back-to-back calls before each side measurement's warm-up
+
+
+def side_settle(fn, seconds: float = SIDE_SETTLE_S) -> None:
+    """Run fn back to back for `seconds` (synchronising every 16 calls), so a
+    side measurement starts with its buffers touched and the clocks loaded,
+    as the headline's settle phase does for the benchmark."""
+    import time
+
+    import torch
+
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(16):
+            fn()
+        torch.cuda.synchronize()
+
+
 def fwd_bwd_measurement(steps: int, warmup: int) -> dict:
     """Forward, backward (ds and dh) and forward+backward on the differentiable
     workload (2^22 samples, 16 filters of 512 taps, N = 4096), timed with HIP
@@ -320,6 +338,7 @@ def fwd_bwd_measurement(steps: int, warmup: int) -> dict:
     stream = torch.cuda.current_stream()
 
     def timed(fn):
+        side_settle(fn)
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -338,7 +357,7 @@ def fwd_bwd_measurement(steps: int, warmup: int) -> dict:
     out = wl.K * wl.Ns
     return {
         "workload": wl.name, "Ns": wl.Ns, "K": wl.K, "M": wl.M, "N": wl.N,
-        "fwd_ms": fwd, "bwd_ms": bwd, "fwd_bwd_ms": both,
+        "fwd_ms": fwd, "bwd_ms": bwd, "fwd_bwd_ms": both, "settle_s": SIDE_SETTLE_S,
         "fwd_samples_per_s": out / (fwd * 1e-3),
         "fwd_bwd_samples_per_s": out / (both * 1e-3),
         "bwd_over_fwd": bwd / fwd,
@@ -360,6 +379,7 @@ def variants_measurement(steps: int, warmup: int) -> dict:
     stream = torch.cuda.current_stream()
 
     def timed(fn):
+        side_settle(fn)
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -391,7 +411,7 @@ def variants_measurement(steps: int, warmup: int) -> dict:
         alg = ybytes * J * wl.K * wl.Ns + 8 * wl.Ns + 8 * wl.K * wl.M
         out[name] = {"workload": wl.name, "ms": ms, "samples_per_s": wl.K * wl.Ns / (ms * 1e-3),
                      "outputs_per_sample": J, "alg_GBps": alg / (ms * 1e-3) / 1e9,
-                     "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                     "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "settle_s": SIDE_SETTLE_S}
         plan.close()
         del y
     del s, h
@@ -403,7 +423,7 @@ def variants_measurement(steps: int, warmup: int) -> dict:
     ms = timed(lambda: plan.forward(s, y))
     alg = 4 * wr.K * wr.Ns + 4 * wr.Ns + 4 * wr.K * wr.M
     out["r2r"] = {"workload": wr.name, "ms": ms, "samples_per_s": wr.K * wr.Ns / (ms * 1e-3),
-                  "alg_GBps": alg / (ms * 1e-3) / 1e9}
+                  "alg_GBps": alg / (ms * 1e-3) / 1e9, "settle_s": SIDE_SETTLE_S}
     plan.close()
     del y
     torch.cuda.empty_cache()
