@@ -77,15 +77,20 @@ def profile_record(workload: str, launch: dict):
 VALU_WAVE_INSTR_PER_S = 256 * 4 / 4 * 2.4e9
 
 
-def floors(alg_bytes: float, rec) -> dict:
+def floors(alg_bytes: float, rec, kernel_ms: float | None = None) -> dict:
     """Lower bounds on the launch time: HBM (algorithmic bytes at the 8 TB/s
     peak) and VALU (the profiled wave64 VALU instructions at the peak issue
-    rate); 'binding' names the larger one."""
+    rate); 'binding' names the larger one.  With the measured launch time,
+    'valu_frac' is the VALU floor over it (the VALU roofline fraction at the
+    peak clock, beside the HBM one that `frac` reports)."""
     hbm_ms = alg_bytes / (HBM_PEAK_GBS * 1e9) * 1e3
     valu = rec.get("valu_instr_per_launch") if rec else None
     valu_ms = valu / VALU_WAVE_INSTR_PER_S * 1e3 if valu else None
     binding = "hbm" if valu_ms is None or hbm_ms >= valu_ms else "valu"
-    return {"hbm_ms": hbm_ms, "valu_ms": valu_ms, "valu_instr_per_launch": valu, "binding": binding}
+    out = {"hbm_ms": hbm_ms, "valu_ms": valu_ms, "valu_instr_per_launch": valu, "binding": binding}
+    if kernel_ms:
+        out["valu_frac"] = valu_ms / kernel_ms if valu_ms else None
+    return out
 
 
 def launch_spread(ms) -> dict:
@@ -636,7 +641,7 @@ def main():
             "kernel_ms": kernel_ms,
             "launch_ms": launch_spread(launch_ms),
             "alg_bytes_per_launch": alg_bytes,
-            "floors": floors(alg_bytes, prof),
+            "floors": floors(alg_bytes, prof, kernel_ms),
         },
         "settle": settle,
     }

@@ -49,3 +49,7 @@ def test_floors_name_the_binding_one():
     f = bench.floors(alg, {"valu_instr_per_launch": 1.2288e9})
     assert f["valu_ms"] == pytest.approx(2.0) and f["binding"] == "valu"
     assert bench.floors(alg, {"valu_instr_per_launch": 1e8})["binding"] == "hbm"
+    # with the measured launch time: the VALU floor over it
+    g = bench.floors(alg, {"valu_instr_per_launch": 1.2288e9}, kernel_ms=4.0)
+    assert g["valu_frac"] == pytest.approx(g["valu_ms"] / 4.0)
+    assert bench.floors(alg, None, kernel_ms=4.0)["valu_frac"] is None
