@@ -1,7 +1,8 @@
-"""hipGraph capture of the single-signal forward (plain, power, R2R) and of the
-adjoint: the launches allocate nothing (backward after reserve_backward) and
-record no memset, so they can be captured once and replayed; every replay
-reads the inputs' current contents and matches the oracle and an eager call."""
+"""hipGraph capture of the single-signal forward (plain, power, R2R, with the
+non-local stage) and of the adjoint: the launches allocate nothing (backward
+after reserve_backward) and record no memset, so they can be captured once
+and replayed; every replay reads the inputs' current contents and matches the
+oracle and an eager call."""
 
 import sys
 
@@ -138,4 +139,31 @@ def test_forward_graph_replays_rows_off_grid(ols, kind):
             if kind == "power":
                 ref = post.power(ref)
         assert np.all(rel_rows(y.cpu().numpy(), ref) <= TOL), rep
+    plan.close()
+
+
+def test_stencil_graph_replays(ols):
+    """A plan with the non-local stage (cubic midpoint interpolation, two
+    outputs per sample) captured once: every replay reads the current input
+    and matches the oracle's stencil of eq. (1)."""
+    print("graph forward stencil", flush=True)
+    Ns, K, M, N = 30001, 3, 200, 1024
+    s, h = workloads.make_signal_filters(Ns, K, M, seed=73)
+    w, left = post.midpoint_interpolation_stencil(1, 2)
+    plan = ols.OLSPlan(dev(h), N=N, stencil=(w, left))
+    sd = dev(s)
+    y = torch.empty((K, 2 * Ns), dtype=torch.complex64, device="cuda")
+    graph = capture(lambda st: plan.forward(sd, y=y, stream=st))
+    for rep in range(3):
+        s2, _ = workloads.make_signal_filters(Ns, 1, 1, seed=800 + rep)
+        sd.copy_(dev(s2))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        ref = post.conv_stencil(s2, h, w, left)
+        assert np.all(rel_rows(y.cpu().numpy(), ref) <= TOL), rep
+        got = y.clone()
+        plan.forward(sd, y=y)
+        torch.cuda.synchronize()
+        assert torch.equal(got, y)
     plan.close()
