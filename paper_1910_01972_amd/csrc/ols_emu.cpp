@@ -117,7 +117,7 @@ std::vector<std::array<float2, Geo<N>::TWR>> lane_twiddles(const std::vector<flo
 
 // Filter spectra in kernel order F[K][8][G][2] (as the device plan stores them).
 // shift_mask != 0: filter r delayed by row_delay(shift_y, shift_el, shift_ns,
-// shift_d, r, shift_mask) samples (output rows off the 64-byte grid), here by
+// shift_d, r, shift_mask) samples (output rows off the 128-byte line grid), here by
 // placing its taps later (the device plan multiplies its spectra by the
 // phase of the delay instead).
 template <int N>
@@ -638,7 +638,7 @@ int ols_emu_backward(int N, const float* s, int64_t Ns, const float* gy, const f
 
 // Batched forward through the kernel dataflow.  Per item: s, y (host), N_s,
 // K, M, N (must be given, 256..4096), D, H; H = 0 takes the library's
-// geometry (default delay, and the row shift of rows off the 64-byte grid).
+// geometry (default delay, and the row shift of rows off the 128-byte line grid).
 // grid = persistent workgroups.
 int ols_emu_batched(int n, const float* const* s, float* const* y, const int64_t* Ns, const float* const* h,
                     const int* K, const int* M, const int* N, const int* D, const int* H, int grid) {

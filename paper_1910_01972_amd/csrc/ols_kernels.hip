@@ -133,7 +133,7 @@ __device__ __forceinline__ void inverse_of_products(float2 (&x)[NF][16], const f
 // Filters r0 .. r0 + SEGS - 1 (those < K) of one filter bank, one transform
 // per G lanes; the body of the plan step and of the batch setup.
 // RowShift: with mask != 0, filter r is delayed by row_delay(y, el, Ns, D,
-// r, mask) samples (output rows off the 64-byte grid).
+// r, mask) samples (output rows off the 128-byte line grid).
 struct SpectraShift {
   const void* y;
   int64_t Ns;
@@ -415,7 +415,7 @@ __device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64
       sv, Ns, F, yv, K, D, H, tw, u0, u1, lds, par, st, shift_mask, K);
 }
 
-// shift_mask: 0, or the row shift of output rows off the 64-byte grid
+// shift_mask: 0, or the row shift of output rows off the 128-byte line grid
 // (row_shift_geometry; F then holds the delayed filters).
 template <int N, int NF, bool POWER, bool REAL>
 __global__ __launch_bounds__(Geo<N>::WG) void ols_forward_kernel(const void* __restrict__ s, int64_t Ns,
@@ -1412,8 +1412,6 @@ struct Kern {
     return stencil_fn_nf<1>(power, real);
   }
   static hipError_t forward(const ols_plan_s* p, const void* s, int64_t Ns, void* y, hipStream_t st) {
-    // output rows off the 64-byte grid run with per-row delayed filters (the
-    // delayed copy is rewritten on the call's stream before the forward)
     // output rows off the 128-byte grid read the plan's spectra for each
     // row's delay (the call only reads the plan)
     const bool float_out = (p->flags & (OLS_REAL | OLS_POST_POWER)) != 0;

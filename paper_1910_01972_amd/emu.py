@@ -114,7 +114,7 @@ def forward(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, gua
 def forward_post(s: np.ndarray, h: np.ndarray, N: int, D: int, H: int, grid: int, post: int, guard: int = 4096,
                  y_offset: int = 0):
     """Forward OLS with flags (1 derivative, 2 power, 4 R2R with float32 s, h
-    and y, 8 the library's row shift for outputs off the 64-byte grid); the
+    and y, 8 the library's row shift for outputs off the 128-byte line grid); the
     output is complex64 [K][N_s], or float32 for power and R2R, inside NaN
     guard bands, starting y_offset elements past a 64-byte aligned address.
     Returns (y, y_guard_ok)."""
@@ -217,7 +217,7 @@ def row_shift(y_addr: int, Ns: int, D: int, r: int, mask: int) -> int:
 def batched(items, grid: int):
     """items: list of dicts with s (complex64 [N_s]), h (complex64 [K][M]), N,
     D, H (H = 0: the library's geometry, including the row shift of outputs
-    off the 64-byte grid) and optionally y_offset (complex elements past a
+    off the 128-byte line grid) and optionally y_offset (complex elements past a
     64-byte aligned address).  Returns the list of outputs y_i [K_i][N_i_s]
     (NaN-prefilled, so an unwritten output stays NaN)."""
     L = emu()

@@ -420,7 +420,7 @@ def test_batched_row_shift_geometry():
 
 
 def test_batched_row_shift_vs_oracle():
-    """The library's batched geometry with outputs off the 64-byte grid (odd
+    """The library's batched geometry with outputs off the 128-byte grid (odd
     N_s, misaligned y): delayed spectra and per-row kept windows give eq. (1)."""
     specs = [(5001, 3, 40, 256, 1), (4003, 2, 30, 512, 0), (20001, 2, 100, 1024, 5), (9003, 4, 513, 2048, 3),
              (30001, 2, 300, 4096, 7), (8000, 3, 64, 1024, 2), (8000, 2, 64, 2048, 0), (7, 2, 3, 256, 4)]
@@ -451,7 +451,7 @@ SHIFT_CASES = [
 
 @pytest.mark.parametrize("Ns,K,M,N,flags,off", SHIFT_CASES)
 def test_forward_row_shift_vs_oracle(Ns, K, M, N, flags, off):
-    """Output rows off the 64-byte grid through the library's rule (filters
+    """Output rows off the 128-byte grid through the library's rule (filters
     delayed per row, kept windows moved with them, hop with room for the
     delay) give eq. (1) and its post-processing."""
     real = bool(flags & 4)
