@@ -68,7 +68,8 @@ typedef enum {
  *   M      filter length, 1 <= M <= N
  *   N      FFT length: power of two in [256, 8192], or 0 to let the library
  *          choose (cost model: FFT work per valid output sample, among
- *          N >= 1024; the shorter lengths run slower per output here)
+ *          N >= 1024, or N >= 2048 for K >= 24 filters; the shorter lengths
+ *          run slower per output there than their work says)
  *   stream the filter spectra are computed on this stream; the plan may be
  *          used on any stream once this work is complete (the call itself
  *          synchronises `stream` before returning, so it is)
@@ -283,7 +284,7 @@ ols_status_t ols_plan_reserve_backward(ols_plan_t plan);
  *   K, M >= 1
  *   N    FFT length of this item: power of two in [256, 4096], or 0 for the
  *        library's choice (cost model: least transform work per kept sample,
- *        among N >= 1024)
+ *        among N >= 1024, or N >= 2048 for K >= 24 filters)
  *   y    device, complex64 [K][N_s], must not overlap s; outputs of different
  *        items must not overlap each other (not checked)
  * Pointers must be 8-byte aligned.

@@ -639,19 +639,26 @@ OLS_HD int default_delay(int N, int M) {
 
 // Cost model for N = 0: transform work per kept output sample, about
 // (K + 1) * 3.2 N log2 N + K * 4 N flops per segment over K * H kept samples,
-// among N >= COST_MODEL_MIN_N.  Compared as exact integers (5x the work,
+// among N >= cost_model_min_n(K).  Compared as exact integers (5x the work,
 // cross-multiplied by the hops) so that the host and the device pick the same
-// N.  N = 256 and 512 are left out: their transforms are narrower than a wave
-// and measured 10-24 % slower per output than N = 1024 on every cell of the
-// 2^25-sample sweep where both fit, although they need up to ~10 % fewer
-// flops (with them out, the model's N is within 6 % of the fastest measured
-// N in all 12 cells, against 24 % before).  Returns 0 if no length in
-// [COST_MODEL_MIN_N, max_n] holds M taps.
+// N.  Lengths whose measured time per output is worse than their flop count
+// says are left out:
+//   * N = 256 and 512: their transforms are narrower than a wave and measured
+//     10-24 % slower per output than N = 1024 on every cell of the
+//     2^25-sample sweep where both fit, although they need up to ~10 % fewer
+//     flops;
+//   * N = 1024 for K >= COST_MODEL_WIDE_K filters: with the inverse
+//     transforms dominating, N = 2048 measured 1-12 % faster per output
+//     (K = 24 .. 64, M = 32, 128, 256, 2^25 samples) although it needs ~7 %
+//     more flops; at K = 8 N = 1024 is 6-7 % faster, as the flops say.
+// Returns 0 if no length in [cost_model_min_n(K), max_n] holds M taps.
 constexpr int COST_MODEL_MIN_N = 1024;
+constexpr int COST_MODEL_WIDE_K = 24;
+OLS_HD int cost_model_min_n(int K) { return K >= COST_MODEL_WIDE_K ? 2 * COST_MODEL_MIN_N : COST_MODEL_MIN_N; }
 OLS_HD int cost_model_fft_length(int K, int M, int max_n) {
   int best = 0;
   unsigned __int128 best_w = 0, best_h = 1;
-  for (int n = COST_MODEL_MIN_N; n <= max_n; n *= 2) {
+  for (int n = cost_model_min_n(K); n <= max_n; n *= 2) {
     if (n < M) continue;
     const int h = n - default_delay(n, M);
     if (h < 1) continue;

@@ -207,17 +207,19 @@ def sweep(reps: int = 10, tune_ns: int = 1 << 22):
 
 def run_config(M: int, K: int, Ns: int, N: int, nf: int, wpc: int, reps: int = 10) -> dict:
     """The forward for one (M, K) on Ns synthetic samples with a fixed FFT
-    length and tiling: reps timed launches after two warm-ups."""
+    length and tiling (0: the library's choice): reps timed launches after
+    two warm-ups.  Reports the configuration that ran."""
     from .ols import OLSPlan
     s, h = synthetic(Ns, K, M, seed=M * 1000 + K)
     y = torch.empty((K, Ns), dtype=torch.complex64, device="cuda")
     plan = OLSPlan(h, N=N)
     plan.set_tiling(nf, wpc)
     ms = _time_forward(plan, s, y, reps)
-    launch = plan.launch()
+    launch, tiling = plan.launch(), plan.tiling()
+    n_used = plan.fft_length()
     plan.close()
-    return {"M": M, "K": K, "Ns": Ns, "N": N, "filters_per_unit": nf, "workgroups_per_cu": wpc, "ms": ms,
-            "grid": launch["grid"]}
+    return {"M": M, "K": K, "Ns": Ns, "N": n_used, "filters_per_unit": tiling["filters_per_unit"],
+            "workgroups_per_cu": tiling["workgroups_per_cu"], "ms": ms, "grid": launch["grid"]}
 
 
 def main(argv=None):

@@ -267,19 +267,22 @@ def test_last_exchange_is_wave_local(N):
 def test_cost_model_choice():
     """The integer cost model picks, for every (K, M), the length with the least
     transform work per kept output, (K+1) 3.2 N log2 N + 4 K N over K H, among
-    powers of two N >= M in [1024, max] (H = N - D, D = M-1 rounded up to 16
-    when that leaves room; N = 256 and 512 measured slower per output whatever
-    their flop count); checked here against the same formula in float64
+    powers of two N >= M in [1024, max], or [2048, max] for K >= 24 filters
+    (H = N - D, D = M-1 rounded up to 16 when that leaves room; N = 256 and
+    512, and N = 1024 with many filters, measured slower per output than
+    their flop count says); checked here against the same formula in float64
     wherever the best two lengths are not within 1e-12 of a tie."""
     def delay(N, M):
         d = ((M - 1) + 15) // 16 * 16
         return d if d <= N - 1 else M - 1
 
     for max_n in (4096, 8192):
-        for K in (1, 2, 3, 8, 16, 64, 1000):
+        for K in (1, 2, 3, 8, 16, 23, 24, 64, 1000):
             for M in (1, 16, 17, 64, 100, 256, 511, 1000, 2048, 3000, 4096, 5000):
                 costs = {}
                 for N in (1024, 2048, 4096, 8192):
+                    if N < (2048 if K >= 24 else 1024):
+                        continue
                     if N > max_n or N < M or N - delay(N, M) < 1:
                         continue
                     H = N - delay(N, M)
@@ -292,6 +295,10 @@ def test_cost_model_choice():
                 if len(order) > 1 and abs(costs[order[0]] - costs[order[1]]) < 1e-12 * costs[order[0]]:
                     continue
                 assert got == order[0], (K, M, max_n, got, costs)
+    # the choices behind the rule: small filters take N = 1024 up to K = 23
+    # filters and N = 2048 from K = 24 on
+    assert [emu.cost_model(K, 32) for K in (1, 8, 16, 23, 24, 64)] == [1024] * 4 + [2048] * 2
+    assert [emu.cost_model(K, 128) for K in (8, 24)] == [1024, 2048]
 
 
 # ----------------------------------------------------------- non-local stage

@@ -136,3 +136,7 @@ def test_run_config_fixed_configuration(ols):
     assert r["N"] == 1024 and r["filters_per_unit"] == 2 and r["ms"] > 0
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     assert r["grid"] == cus
+    # zeros: the library's configuration, reported as it ran (many short
+    # filters: the cost model's N = 2048, two filters per unit)
+    r = tuner.run_config(32, 24, 1 << 16, 0, 0, 0, reps=2)
+    assert r["N"] == 2048 and r["filters_per_unit"] == 2 and r["workgroups_per_cu"] >= 1
