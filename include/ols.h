@@ -128,11 +128,13 @@ ols_status_t ols_plan_update_filters(ols_plan_t plan, const void* h, ols_stream_
  * ols_plan_set_hop -- choose the segment stride H (valid outputs kept per
  * segment).  The paper keeps L = N - M + 1 samples per segment and states
  * that the result does not depend on the segment size (sec. 3.2), so any
- * 1 <= H <= N - M + 1 gives the same output.  By default the library uses the
- * largest H whose segments start on 16-sample (128-byte) boundaries:
- * D = M - 1 rounded up to a multiple of 16 (when that still leaves room),
- * H = N - D.  H = 0 restores the default.  With a stencil (below) the limit is
- * 1 <= H <= N - (M - 1 + left) - right.  Errors: INVALID_VALUE.
+ * 1 <= H <= N - Me + 1 gives the same output, with Me = M, or M + 1 for a plan
+ * with OLS_POST_DERIVATIVE (the derivative is folded into the filter as one
+ * more tap).  By default the library uses the largest H whose segments start
+ * on 16-sample (128-byte) boundaries: D = Me - 1 rounded up to a multiple of
+ * 16 (when that still leaves room), H = N - D.  H = 0 restores the default.
+ * With a stencil (below) the limit is 1 <= H <= N - (Me - 1 + left) - right.
+ * Errors: INVALID_VALUE.
  */
 ols_status_t ols_plan_set_hop(ols_plan_t plan, int32_t H);
 
@@ -157,8 +159,9 @@ ols_status_t ols_plan_set_hop(ols_plan_t plan, int32_t H);
  *           left + 1 + right <= 8.
  *   w       host array of J*T float32 weights, read during the call only.
  * Each segment keeps only outputs whose neighbours are unaliased: the first
- * kept position D >= M - 1 + left (M + 1 with the derivative) and the hop
- * H <= N - D - right, so M - 1 + left + right <= N - 1 is required; the
+ * kept position D >= Me - 1 + left (Me as for ols_plan_set_hop: M, or M + 1
+ * with the derivative) and the hop H <= N - D - right, so
+ * Me - 1 + left + right <= N - 1 is required; the
  * default hop is N - D - right rounded down to a multiple of 16 samples (when
  * at least 16), which keeps segments on the 128-byte output grid.  The call
  * resets the hop to that default and the tiling to one filter per unit and
