@@ -228,10 +228,19 @@ __global__ void ols_spectra_delays_kernel(const float2* __restrict__ F, int K, i
 // second register set; the two sets swap roles from one unit to the next (the
 // loop is unrolled by two so that no register copy is needed).  It costs a
 // second set of spectrum registers: with one filter per unit it measured
-// 2-7 % faster (N = 512, 2048, 4096, 8192; 2-3 % slower at N = 1024), with
-// two filters per unit the extra 64 registers halve the occupancy.
+// 2-7 % faster (N = 512, 2048, 4096, 8192; 2-3 % slower at N = 1024 while
+// that kernel ran three workgroups per CU), with two filters per unit the
+// extra 64 registers halve the occupancy.  prefetch_spectra is the rule of
+// the batched kernel's bodies; the single-signal kernel also prefetches at
+// N = 1024 for complex outputs: that kernel now needs more than 168 VGPRs
+// anyway (two workgroups per CU either way), and prefetch measured 3-4 %
+// faster with 8 or 16 filters, level with 1 or 24, and 2 % faster on one
+// filter over 2^20 samples.  The power kernel (167 VGPRs, three workgroups
+// per CU without it) does not.
 template <int N, int NF>
 constexpr bool prefetch_spectra() { return NF == 1 && N != 1024; }
+template <int N, int NF, bool POWER, bool REAL>
+constexpr bool prefetch_spectra_single() { return NF == 1 && (N != 1024 || (!POWER && !REAL)); }
 
 // Exchange buffers of a forward kernel (double-buffered only across waves),
 // and its LDS: the buffers, plus, for the non-local stage with transforms no
@@ -411,7 +420,7 @@ __device__ __forceinline__ void forward_range(const void* __restrict__ sv, int64
   float2 tw[Geo<N>::TWR];
   load_lane_twiddles<N>(tw, twt, threadIdx.x % Geo<N>::G);
   // the stage's accumulators take the registers of the spectrum prefetch
-  forward_units<N, NF, POWER, REAL, SMODE, prefetch_spectra<N, NF>() && !STAGE, STAGE>(
+  forward_units<N, NF, POWER, REAL, SMODE, prefetch_spectra_single<N, NF, POWER, REAL>() && !STAGE, STAGE>(
       sv, Ns, F, yv, K, D, H, tw, u0, u1, lds, par, st, shift_mask, K);
 }
 
