@@ -238,7 +238,8 @@ def sweep_measurement(launches: int = 10, rounds: int = 3) -> dict:
         y = torch.empty((K, Ns), dtype=torch.complex64, device="cuda")
         plans = {N: OLSPlan(h, N=N) for N in tuner.CANDIDATES if N >= M and 4 * (N - M + 1) >= N}
         auto = OLSPlan(h, N=0)
-        chosen = auto.info()["N"]
+        chosen, hop = auto.info()["N"], auto.info()["H"]
+        tiling, grid = auto.tiling(), auto.launch()["grid"]
         auto.close()
         times = {N: [] for N in plans}
         for p in plans.values():
@@ -258,8 +259,14 @@ def sweep_measurement(launches: int = 10, rounds: int = 3) -> dict:
         best = min(med, key=med.get)
         alg = 8.0 * K * Ns + 8.0 * Ns + 8.0 * K * M
         frac = lambda ms: alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
-        cells.append({"M": M, "K": K, "cost_model_N": chosen, "cost_model_ms": med[chosen],
-                      "cost_model_frac": frac(med[chosen]), "best_N": best, "best_ms": med[best],
+        # the cost model's configuration: hop H, tiling, and segments per
+        # persistent workgroup S (average over the grid)
+        cells.append({"M": M, "K": K, "cost_model_N": chosen, "hop": hop,
+                      "filters_per_unit": tiling["filters_per_unit"],
+                      "workgroups_per_cu": tiling["workgroups_per_cu"],
+                      "segments_per_workgroup": round(-(-Ns // hop) / grid, 2),
+                      "cost_model_ms": med[chosen], "cost_model_frac": frac(med[chosen]),
+                      "cost_model_GBps": alg / (med[chosen] * 1e-3) / 1e9, "best_N": best, "best_ms": med[best],
                       "best_frac": frac(med[best]), "samples_per_s": K * Ns / (med[chosen] * 1e-3),
                       "ms_per_N": {str(N): round(v, 4) for N, v in med.items()}})
         for p in plans.values():
