@@ -148,6 +148,17 @@ def test_auto_fft_length(ols):
     assert np.all(rel_rows(y, conv.direct_conv(s, h)) <= TOL)
 
 
+@pytest.mark.parametrize("K,N_expected", [(23, 1024), (24, 2048), (31, 2048)])
+def test_auto_fft_length_many_filters(ols, K, N_expected):
+    """The library's length for short filters: N = 1024 up to 23 filters,
+    N = 2048 from 24 on (two filters per unit; K = 31 leaves a ragged last
+    group); every row matches eq. (1) in guarded outputs."""
+    s, h = workloads.make_signal_filters(30011, K, 32, seed=K)
+    y, info = run_case(ols, s, h, 0)
+    assert info["N"] == N_expected, info
+    assert np.all(rel_rows(y, conv.direct_conv(s, h)) <= TOL)
+
+
 def test_hop_invariance(ols):
     """sec. 3.2: the result does not depend on the segment size or hop."""
     s, h = workloads.make_signal_filters(40000, 2, 200, seed=5)
