@@ -87,6 +87,7 @@ def run_guarded(plan, s, K, cols, float_out, offset=0):
 CASES = [
     # (Ns, K, M, N, flags, stencil); flags: 1 derivative, 2 power, 4 R2R
     (1, 1, 1, 256, 0, "midpoint_cubic"),
+    (2, 2, 5, 256, 0, "ahead4"),                # every tap past the sample reads the tail
     (200, 2, 3, 256, 0, "ahead4"),              # fewer samples than one segment
     (5001, 3, 40, 256, 0, "wide3"),
     (5001, 3, 40, 256, 2, "midpoint_cubic"),
@@ -102,6 +103,8 @@ CASES = [
     (50000, 2, 2000, 8192, 0, "midpoint_cubic"),
     (50001, 2, 8185, 8192, 0, "difference"),    # hop 1
     # R2R: two real segments per transform, each with its own stencil outputs
+    (1, 2, 3, 256, 4, "midpoint_cubic"),        # one real sample: the pair's second segment is empty
+    (3, 1, 2, 256, 4 | 2, "behind"),            # all taps before the sample: zero history
     (3001, 3, 40, 256, 4, "midpoint_cubic"),
     (20000, 4, 100, 1024, 4 | 2, "wide3"),
     (65536, 6, 256, 2048, 4, "midpoint_cubic"),
@@ -219,6 +222,23 @@ def test_stencil_argument_errors(ols):
         plan.forward(dev(s), y=torch.empty((2, 3000), dtype=torch.complex64, device="cuda"))
     with pytest.raises(ols.OLSError):
         plan.backward(dev(s), dev(workloads.make_grad(2, 3000, seed=83)))
+    plan.close()
+
+
+def test_stencil_empty_signal(ols):
+    """N_s = 0 through the C ABI on a stencil plan: a successful no-op that
+    writes nothing (a sentinel buffer stays as it was)."""
+    from paper_1910_01972_amd._lib import lib
+    say("stencil empty signal")
+    w, left = STENCILS["midpoint_cubic"]
+    _, h = workloads.make_signal_filters(1, 2, 16, seed=85)
+    plan = ols.OLSPlan(dev(h), N=256, stencil=(w, left))
+    s = torch.zeros(8, dtype=torch.complex64, device="cuda")
+    y = torch.full((64,), complex(3.0, -1.0), dtype=torch.complex64, device="cuda")
+    P = ctypes.c_void_p
+    assert lib().ols_forward(plan.handle, P(s.data_ptr()), 0, P(y.data_ptr()), None) == 0
+    torch.cuda.synchronize()
+    assert bool((y == complex(3.0, -1.0)).all()), "an empty call wrote outputs"
     plan.close()
 
 
